@@ -1,0 +1,186 @@
+/*
+ * fastpfp.h -- C ABI of the MI355X FastPFP library (libfastpfp.so).
+ *
+ * FastPFP (Lu, Huang & Liu, "A Fast Projected Fixed-Point Algorithm for
+ * Large Graph Matching", arXiv 1207.1114) relaxes the graph-matching QAP of
+ * Sec. 3, eqs. (3)-(4),
+ *     max_X  1/2 tr(X^T A X A') + lambda tr(X^T K)
+ *     s.t.   X 1 <= 1, X^T 1 = 1, X >= 0                (Sec. 4, relaxed set)
+ * and iterates Algorithm 1:
+ *     Y[0:n,0:n'] = A X A' + lambda K                        (step 3)
+ *     repeat Y = P2(P1(Y)) until max|dY| < tol_inner         (steps 4-7,
+ *                                                              eqs. P1, P2)
+ *     X = (1 - alpha) X + alpha Y[0:n,0:n']                   (step 8, eq. fastPFP)
+ *     X = X / max(X)                                          (step 9)
+ * until max|dX| < tol_outer (Sec. 5, convergence criteria).
+ * In this ABI the paper's A' is called B.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major float32.  Pointers are DEVICE pointers unless the
+ *   argument name ends in _host.  ld* is the row pitch in elements
+ *   (ld >= number of columns).
+ * - A (n x n) and B (n' x n') must be symmetric (undirected graphs, Sec. 3);
+ *   symmetry is assumed, not checked.
+ * - Either orientation is accepted: with N = max(n, n'), the smaller side gets
+ *   unit sums and the larger side sums <= 1 (the paper writes the n >= n'
+ *   case; the other one is its transpose).
+ * - The caller owns every buffer it passes; the library never frees one.  A
+ *   handle owns its device workspace, grown on demand by solve calls.
+ * - All device work is enqueued on the handle's stream; solve/project calls
+ *   return after synchronising that stream, when *info is valid.
+ * - One handle per host thread.  No C++ exception crosses this ABI; every
+ *   function returns a status, and fastpfp_last_error() describes the last
+ *   failure on a handle.
+ * - Non-convergence is not an error: it returns FASTPFP_OK with
+ *   info.converged = 0.
+ */
+#ifndef FASTPFP_H
+#define FASTPFP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FASTPFP_ABI_VERSION 1
+
+typedef struct fastpfp_ctx* fastpfp_t;
+
+typedef enum {
+  FASTPFP_OK = 0,
+  FASTPFP_ERR_INVALID_ARG = 1, /* bad pointer, NaN/negative parameter, ... */
+  FASTPFP_ERR_SHAPE = 2,       /* size or leading dimension out of range   */
+  FASTPFP_ERR_HIP = 3,         /* a HIP runtime call failed                */
+  FASTPFP_ERR_NOMEM = 4,       /* device workspace allocation failed       */
+  FASTPFP_ERR_NUMERIC = 5,     /* NaN/Inf met, or max(X) <= 0 in step 9    */
+  FASTPFP_ERR_TIMEOUT = 6,     /* a device-side wait hit its time limit    */
+  FASTPFP_ERR_UNSUPPORTED = 7  /* valid request this build cannot run      */
+} fastpfp_status;
+
+/* Precision of the two products A X B (step 3).  The projection, the update
+ * and all reductions always run in float32, with the global sum 1^T Y 1 in
+ * float64. */
+enum { FASTPFP_FP32 = 0, FASTPFP_BF16 = 1 };
+
+/* Starting point X0 (Algorithm 1, step 1; initialisation paragraph after it) */
+enum { FASTPFP_INIT_UNIFORM = 0, /* X0 = c 1 1^T                     */
+       FASTPFP_INIT_USER = 1 };  /* X0 read from the X buffer        */
+
+/* Discretisation (Sec. 4.5) */
+enum { FASTPFP_HUNGARIAN = 0, /* maximum-weight assignment of X         */
+       FASTPFP_GREEDY = 1 };  /* the paper's greedy rule (from SM)      */
+
+typedef struct {
+  double lambda;     /* >= 0, weight of K in eq. (3); K may be NULL iff 0    */
+  double alpha;      /* step size of eq. fastPFP, in (0, 1]; paper uses 0.5  */
+  double tol_outer;  /* eps1 > 0: stop when max|X_{t+1} - X_t| < eps1        */
+  double tol_inner;  /* eps2 > 0: inner stop when max|Y_{u+1} - Y_u| < eps2  */
+  int max_outer;     /* I0 >= 1: cap on outer steps                          */
+  int max_inner;     /* I1 >= 1: cap on inner passes per outer step          */
+  int precision;     /* FASTPFP_FP32 or FASTPFP_BF16                         */
+  int init;          /* FASTPFP_INIT_UNIFORM or FASTPFP_INIT_USER            */
+  double init_scale; /* UNIFORM: c; 0 selects c = 1/max(n, n')               */
+  int normalize_max; /* 1: step 9 (X /= max X) as in Algorithm 1; 0: skip   */
+  int team_size;     /* workgroups per pair; 0 lets the library choose       */
+} fastpfp_params;
+
+typedef struct {
+  int outer_iters;       /* outer steps taken                                */
+  int inner_iters_total; /* inner passes summed over outer steps             */
+  int inner_iters_max;   /* largest inner pass count of one outer step      */
+  int inner_capped;      /* outer steps whose inner loop stopped at I1       */
+  int converged;         /* 1 iff the last outer step met eps1               */
+  int status;            /* fastpfp_status of this pair                      */
+  double eps1_last;      /* max|X_{t+1} - X_t| of the last outer step        */
+  double eps2_last;      /* max|Y_{u+1} - Y_u| of the last inner pass        */
+  double kernel_ms;      /* device time of the launch that solved the pair   */
+} fastpfp_info;
+
+/* Fills *p with the defaults: lambda 0, alpha 0.5, eps1 1e-6, eps2 1e-8,
+ * I0 = I1 = 1000, FP32, uniform start with c = 1/max(n,n'), step 9 on. */
+fastpfp_status fastpfp_params_default(fastpfp_params* p);
+
+/* Creates a handle bound to HIP device `device` and to `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  max_n / max_np bound the sizes
+ * later calls may pass (>= 1).  No device memory is allocated here. */
+fastpfp_status fastpfp_create(fastpfp_t* h, int device, int max_n, int max_np,
+                              void* hip_stream);
+fastpfp_status fastpfp_destroy(fastpfp_t h);
+
+/* Solves one pair with Algorithm 1.
+ *   A: n x n (lda), B: n' x n' (ldb), K: n x n' (ldk; NULL iff lambda == 0).
+ *   X: n x n' (ldx).  In: X0 when p->init == FASTPFP_INIT_USER (ignored
+ *      otherwise).  Out: the final iterate X.
+ *   Y_state: NULL, or an N x N buffer (row pitch N), N = max(n, n'), holding
+ *      the slacked matrix Y of Sec. 4.3.  In: its slack part (the entries
+ *      outside the leading n x n' block) seeds the slack; Out: Y after the
+ *      last inner loop.  NULL starts the slack at zero (the paper's Y = 0).
+ *   info: host pointer, filled on return (may be NULL).
+ * Errors: INVALID_ARG for null/ill-formed arguments, SHAPE when n or n'
+ * exceed the handle's bounds or ld < columns, NUMERIC on NaN/Inf, TIMEOUT if
+ * a device wait gave up; X is unspecified after an error. */
+fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np,
+                             const float* A, int lda,
+                             const float* B, int ldb,
+                             const float* K, int ldk,
+                             const fastpfp_params* p,
+                             float* X, int ldx,
+                             float* Y_state,
+                             fastpfp_info* info);
+
+/* Solves `batch` independent pairs in one persistent launch.
+ *   n_host[b], np_host[b]: sizes of pair b.
+ *   A + offA_host[b]: pair b's A, dense n x n (row pitch n); likewise
+ *   B + offB_host[b] (n' x n'), K + offK_host[b] (n x n'; K may be NULL iff
+ *   lambda == 0), X + offX_host[b] (n x n', in/out as in fastpfp_solve).
+ *   Offsets are element counts.  infos_host: batch entries (may be NULL).
+ * Every pair runs the same arithmetic as fastpfp_solve with the same team
+ * size, so a pair's result does not depend on its batch mates.  A pair that
+ * fails (e.g. NUMERIC) is reported in its info.status; the others complete,
+ * and the call returns the first failing status. */
+fastpfp_status fastpfp_solve_batched(fastpfp_t h, int batch,
+                                     const int* n_host, const int* np_host,
+                                     const float* A, const int64_t* offA_host,
+                                     const float* B, const int64_t* offB_host,
+                                     const float* K, const int64_t* offK_host,
+                                     const fastpfp_params* p,
+                                     float* X, const int64_t* offX_host,
+                                     fastpfp_info* infos_host);
+
+/* Runs Algorithm 1's inner repeat (steps 4-7: eqs. P1 then P2 per pass) on
+ * one square N x N matrix Y (row pitch N), in place, until
+ * max|Y_{u+1} - Y_u| < tol or max_inner passes.  info->inner_iters_total
+ * receives the pass count and info->eps2_last the last max|dY|.  Exposed so
+ * the projection can be checked and timed on its own. */
+fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
+                               int max_inner, int team_size,
+                               fastpfp_info* info);
+
+/* Discretises a host matrix X (n x n', ldx) into a partial permutation
+ * (Sec. 4.5).  method: FASTPFP_HUNGARIAN (maximise sum_i X[i, m(i)] over
+ * injective maps of the smaller side) or FASTPFP_GREEDY (repeatedly take
+ * the largest remaining entry, ties to the smallest row-major index, and
+ * remove its row and column).  match_host[i] receives the column matched to
+ * row i, or -1.  score (nullable) receives sum_i X[i, match[i]] in float64.
+ * Host-only; needs no handle or GPU. */
+fastpfp_status fastpfp_discretize(int n, int np, const float* X_host, int ldx,
+                                  int method, int32_t* match_host,
+                                  double* score);
+
+/* Copies the eps1 trace (max|X_{t+1} - X_t| per outer step) of the last
+ * fastpfp_solve on this handle into out_host (up to cap values); returns the
+ * number written in *count. */
+fastpfp_status fastpfp_get_trace(fastpfp_t h, double* out_host, int cap,
+                                 int* count);
+
+const char* fastpfp_status_string(fastpfp_status s);
+const char* fastpfp_last_error(fastpfp_t h);
+int fastpfp_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTPFP_H */
