@@ -1,0 +1,183 @@
+"""Benchmark: matched pairs/s of the FastPFP iteration at n = n' = 1000.
+
+One step solves the whole n=1000 metric set (32 seeded synthetic pairs of
+the config-1 workload: Bernoulli(0.1) U(0,1) weighted graphs, relabelled
+copies with N(0, 0.05^2) edge noise, 16-d attributes, Gaussian K, lambda 1,
+alpha 0.5) to convergence in one persistent launch, inputs resident in HBM.
+Discretisation (Hungarian) runs after the timed region.
+
+Prints one JSON line.  ``roofline`` describes the persistent kernel (the only
+kernel of a step): its inner projection passes are ALU-bound with Y held in
+registers, so ``achieved`` counts 7 float32 operations per entry per pass
+(P1: 2 adds, P2: 1 max, row/column sums: 2 adds, max|dY|: 1 sub + 1 max)
+over the kernel's average launch time measured with HIP events on the
+library's stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("matched pairs/s at n=1000 (plain FP32 vs BF16+warm start); "
+          "A·X·B TFLOP/s")
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz for non-FMA, non-packed
+# float32 VALU instructions (the 157.3 TFLOP/s vector figure counts an FMA
+# as two operations and packed FP32 as two lanes; this build uses neither).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+OPS_PER_ENTRY_PASS = 7
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--pairs", type=int, default=32)
+    ap.add_argument("--n", type=int, default=1000)
+    ap.add_argument("--team-size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-passes", type=int, default=300,
+                    help="inner passes of the oracle timed for the baseline")
+    return ap.parse_args()
+
+
+def make_inputs(torch, n_pairs, n):
+    from paper_1207_1114_amd import synth
+    pairs = [synth.config1_pair(i, n=n) for i in range(n_pairs)]
+    N = n * n
+    A = torch.empty(n_pairs * N, dtype=torch.float32, device="cuda:0")
+    B = torch.empty_like(A)
+    K = torch.empty_like(A)
+    X = torch.zeros_like(A)
+    for i, p in enumerate(pairs):
+        sl = slice(i * N, (i + 1) * N)
+        A[sl] = torch.from_numpy(p.A.ravel().astype(np.float32))
+        B[sl] = torch.from_numpy(p.B.ravel().astype(np.float32))
+        K[sl] = torch.from_numpy(p.K.ravel().astype(np.float32))
+    offs = [i * N for i in range(n_pairs)]
+    return pairs, A.view(-1, 1), B.view(-1, 1), K.view(-1, 1), X.view(-1, 1), offs
+
+
+def cpu_baseline(pair, gpu_infos, passes):
+    """Oracle time of one full pair, projected from a timed sample: one
+    outer step's two products plus `passes` inner passes of the FP64 oracle
+    on pair 0, scaled by the outer / inner counts the solve needed."""
+    from oracle import fastpfp_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([d.get("num_threads", 1)
+                            for d in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count()
+    n, m = pair.n, pair.np_
+    X = O.uniform_x0(n, m)
+    t0 = time.perf_counter()
+    G = O.gradient(pair.A, X, pair.B, pair.K, pair.lam)
+    t_gemm = time.perf_counter() - t0
+    Y = np.zeros((max(n, m), max(n, m)))
+    Y[:n, :m] = G
+    t0 = time.perf_counter()
+    O.inner_projection(Y, 0.0 + 1e-300, passes)
+    t_pass = (time.perf_counter() - t0) / passes
+    outer = gpu_infos[0]["outer_iters"]
+    inner = gpu_infos[0]["inner_iters_total"]
+    t_pair = outer * t_gemm + inner * t_pass
+    return {"value": 1.0 / t_pair, "unit": "pairs/s",
+            "cores": int(blas_threads), "kind": "oracle",
+            "sample": (f"FP64 oracle on config-1 pair 0: 1 gradient "
+                       f"({t_gemm:.3f} s) + {passes} inner passes "
+                       f"({t_pass * 1e3:.2f} ms each), projected to the pair's "
+                       f"{outer} outer steps / {inner} inner passes; "
+                       f"elementwise NumPy runs on 1 thread, products on "
+                       f"{blas_threads} BLAS threads"),
+            "seconds_per_pair": t_pair}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
+              "multi-GPU sharding of this path is described in DESIGN.md but "
+              "not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1207_1114_amd import fastpfp as F
+    from oracle import fastpfp_oracle as O
+
+    torch.cuda.init()
+    pairs, A, B, K, X, offs = make_inputs(torch, args.pairs, args.n)
+    n = args.n
+    S = F.Solver(n, n)
+    prm = F.default_params(lambda_=1.0, team_size=args.team_size)
+    ns, nps = [n] * args.pairs, [n] * args.pairs
+
+    def step():
+        return S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs,
+                               prm)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_infos = []
+    for _ in range(args.steps):
+        all_infos.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * args.pairs / dt
+
+    infos = all_infos[-1]
+    kernel_ms = float(np.mean([inf[0]["kernel_ms"] for inf in all_infos]))
+    passes = sum(i["inner_iters_total"] for i in infos)
+    ops = OPS_PER_ENTRY_PASS * float(n * n) * passes
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    gemm_flops = sum(i["outer_iters"] for i in infos) * 2.0 * n * n * (2 * n)
+
+    Xh = X.view(args.pairs, n, n).cpu().numpy()
+    acc = []
+    for i, p in enumerate(pairs):
+        m, _ = F.discretize(Xh[i])
+        acc.append(O.accuracy(m.astype(np.int64), p.perm))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"config-1 metric set: {args.pairs} seeded "
+                                f"synthetic pairs, n=n'={n}, edge p=0.1, "
+                                "noise 0.05, 16-d attributes, lambda=1, "
+                                "alpha=0.5, eps1=1e-6, eps2=1e-8, "
+                                "I0=I1=1000, FP32 products"),
+                   "pairs_per_step": args.pairs, "n": n, "precision": "fp32",
+                   "team_size": args.team_size or "auto"},
+        "roofline": {"bound": "alu", "achieved": achieved,
+                     "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "fastpfp_persistent",
+                     "avg_launch_ms": kernel_ms,
+                     "work_per_launch": (f"{passes} inner passes x {n}^2 "
+                                         f"entries x {OPS_PER_ENTRY_PASS} ops")},
+        "gemm_tflops_in_launch": gemm_flops / (kernel_ms * 1e-3) / 1e12,
+        "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
+        "inner_iters_mean": float(np.mean([i["inner_iters_total"]
+                                           for i in infos])),
+        "accuracy_mean": float(np.mean(acc)),
+        "converged": int(sum(i["converged"] for i in infos)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,490 @@
+// Host side of the FastPFP C ABI: validation, team planning, workspace, and
+// the launch of the persistent kernel (fastpfp_kernels.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fastpfp.h"
+#include "fastpfp_internal.h"
+
+extern "C" hipError_t fpfp_launch_persistent(const fpfp::LaunchDesc* L,
+                                             int grid, hipStream_t stream);
+extern "C" hipError_t fpfp_occupancy(int* blocks_per_cu);
+
+struct fastpfp_ctx {
+  int device = 0;
+  int max_n = 0, max_np = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int cu_count = 0;
+  int occupancy = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<double> trace;
+};
+
+namespace {
+
+fastpfp_status fail(fastpfp_t h, fastpfp_status s, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(h, call)                                                     \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail((h), FASTPFP_ERR_HIP, "%s failed: %s", #call,             \
+                  hipGetErrorString(e_));                                   \
+  } while (0)
+
+struct Plan {
+  int W, TR, TC;
+};
+
+// The tile grid of a team depends on its size W (a power of two) only:
+// TR = 2^ceil(log2(W)/2) tile rows by TC = W / TR tile columns, so a pair is
+// cut into the same tiles -- and computed with the same rounding -- whether it
+// is solved alone or in a batch with the same W.  The grid fits N when every
+// tile fits the register tile (kTileRows x kTileCols).
+void grid_for(int W, Plan* pl) {
+  int lg = 0;
+  while ((1 << lg) < W) ++lg;
+  pl->W = W;
+  pl->TR = 1 << ((lg + 1) / 2);
+  pl->TC = W / pl->TR;
+}
+
+bool grid_fits(const Plan& pl, int N) {
+  return pl.TR <= fpfp::kMaxTeamSide && pl.TC <= fpfp::kMaxTeamSide &&
+         (N + pl.TR - 1) / pl.TR <= fpfp::kTileRows &&
+         (N + pl.TC - 1) / pl.TC <= fpfp::kTileCols;
+}
+
+// want > 0: that team size (must be a power of two that fits N);
+// want == 0: the smallest power of two that fits N.
+bool plan_team(int N, int want, Plan* pl) {
+  if (want > 0) {
+    if ((want & (want - 1)) != 0) return false;
+    grid_for(want, pl);
+    return grid_fits(*pl, N);
+  }
+  for (int W = 1; W <= fpfp::kMaxTeamSide * fpfp::kMaxTeamSide; W *= 2) {
+    grid_for(W, pl);
+    if (grid_fits(*pl, N)) return true;
+  }
+  return false;
+}
+
+fastpfp_status check_params(fastpfp_t h, const fastpfp_params* p) {
+  if (!p) return fail(h, FASTPFP_ERR_INVALID_ARG, "params is NULL");
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (!(p->alpha > 0.0 && p->alpha <= 1.0))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "alpha must lie in (0, 1]");
+  if (!(p->tol_outer > 0.0) || !std::isfinite(p->tol_outer) ||
+      !(p->tol_inner > 0.0) || !std::isfinite(p->tol_inner))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "tolerances must be finite and > 0");
+  if (p->max_outer < 1 || p->max_inner < 1)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "iteration caps must be >= 1");
+  if (p->precision != FASTPFP_FP32 && p->precision != FASTPFP_BF16)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->precision == FASTPFP_BF16)
+    return fail(h, FASTPFP_ERR_UNSUPPORTED, "BF16 products are not built yet");
+  if (p->init != FASTPFP_INIT_UNIFORM && p->init != FASTPFP_INIT_USER)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown init %d", p->init);
+  if (!(p->init_scale >= 0.0) || !std::isfinite(p->init_scale))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "init_scale must be finite and >= 0");
+  if (p->team_size < 0)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "team_size must be >= 0");
+  return FASTPFP_OK;
+}
+
+// Workspace layout of one launch, in bytes from the workspace base.
+struct Layout {
+  size_t pairs, infos, queue, trace, xbuf, wsT, wsY, total;
+  long long xbuf_stride, wsT_stride, wsY_stride;
+};
+
+Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
+                  int max_nnp, int max_outer, bool need_y, bool need_trace) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  Layout L{};
+  size_t o = 0;
+  L.pairs = o;
+  o = up(o + sizeof(fpfp::PairDesc) * num_pairs);
+  L.infos = o;
+  o = up(o + sizeof(fpfp::DevInfo) * num_pairs);
+  L.queue = o;
+  o = up(o + 16);
+  L.trace = o;
+  o = up(o + (need_trace ? sizeof(float) * max_outer : 0));
+  L.xbuf_stride = 2 * fpfp::xbuf_words_per_parity(pl.TR, pl.TC, pl.W, maxN);
+  L.xbuf = o;
+  o = up(o + sizeof(uint64_t) * L.xbuf_stride * num_teams);
+  L.wsT_stride = ((long long)max_nnp + 63) & ~63LL;
+  L.wsT = o;
+  o = up(o + sizeof(float) * L.wsT_stride * num_teams);
+  L.wsY_stride = need_y ? (((long long)maxN * maxN + 63) & ~63LL) : 0;
+  L.wsY = o;
+  o = up(o + sizeof(float) * L.wsY_stride * num_teams);
+  L.total = o;
+  return L;
+}
+
+fastpfp_status ensure_ws(fastpfp_t h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return FASTPFP_OK;
+  if (h->ws) {
+    hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = std::max(bytes, size_t(1) << 20);
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    h->ws = nullptr;
+    return fail(h, FASTPFP_ERR_NOMEM, "cannot allocate %zu bytes of workspace",
+                want);
+  }
+  h->ws_bytes = want;
+  return FASTPFP_OK;
+}
+
+struct PairIn {
+  int n, np;
+  const float *A, *B, *K;
+  float* X;
+  float* Y;
+  int lda, ldb, ldk, ldx;
+};
+
+// Plans, launches and waits for one persistent launch over `pairs`.
+fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
+                   const fastpfp_params* p, int mode, int max_inner,
+                   double tol_in, int team_req, bool want_trace,
+                   fastpfp_info* infos) {
+  HIPCHK(h, hipSetDevice(h->device));
+  int maxN = 1, max_nnp = 1;
+  for (auto& q : pairs) {
+    maxN = std::max(maxN, std::max(q.n, q.np));
+    max_nnp = std::max(max_nnp, q.n * q.np);
+  }
+  Plan pl;
+  if (!plan_team(maxN, team_req, &pl))
+    return fail(h, FASTPFP_ERR_INVALID_ARG,
+                "team_size %d is not a power of two whose tiles fit N = %d",
+                team_req, maxN);
+  int G = std::min(512, h->occupancy * h->cu_count);
+  G -= G % fpfp::kXcds;
+  if (pl.W > G)
+    return fail(h, FASTPFP_ERR_UNSUPPORTED,
+                "N = %d needs %d co-resident workgroups; %d fit", maxN, pl.W, G);
+  const int num_teams = std::max(1, std::min((int)pairs.size(), G / pl.W));
+  bool need_y = false;
+  for (auto& q : pairs) need_y |= (q.Y == nullptr);
+  const int max_outer = mode == fpfp::kModeSolve ? p->max_outer : 1;
+  Layout lay = layout_for((int)pairs.size(), num_teams, pl, maxN, max_nnp,
+                          max_outer, need_y, want_trace);
+  fastpfp_status st = ensure_ws(h, lay.total);
+  if (st != FASTPFP_OK) return st;
+  char* base = (char*)h->ws;
+
+  std::vector<fpfp::PairDesc> pd(pairs.size());
+  for (size_t b = 0; b < pairs.size(); ++b) {
+    const PairIn& q = pairs[b];
+    fpfp::PairDesc& d = pd[b];
+    std::memset(&d, 0, sizeof d);
+    d.A = q.A;
+    d.B = q.B;
+    d.K = (p && p->lambda > 0.0) ? q.K : nullptr;
+    d.X = q.X;
+    d.Y = q.Y;
+    d.trace = (want_trace && b == 0) ? (float*)(base + lay.trace) : nullptr;
+    d.info = (fpfp::DevInfo*)(base + lay.infos) + b;
+    d.n = q.n;
+    d.np = q.np;
+    d.N = std::max(q.n, q.np);
+    d.lda = q.lda;
+    d.ldb = q.ldb;
+    d.ldk = q.ldk;
+    d.ldx = q.ldx;
+    d.mode = mode;
+    d.max_inner = max_inner;
+    d.tol_in = (float)tol_in;
+    if (mode == fpfp::kModeSolve) {
+      d.init_user = p->init == FASTPFP_INIT_USER;
+      d.y_user = q.Y != nullptr;
+      d.normalize = p->normalize_max != 0;
+      d.max_outer = p->max_outer;
+      d.precision = p->precision;
+      d.lam = (float)p->lambda;
+      d.alpha = (float)p->alpha;
+      d.tol_out = (float)p->tol_outer;
+      d.init_c = (float)(p->init_scale > 0.0 ? p->init_scale
+                                             : 1.0 / (double)d.N);
+    } else {
+      d.y_user = 1;
+    }
+  }
+  fpfp::LaunchDesc L;
+  std::memset(&L, 0, sizeof L);
+  L.pairs = (const fpfp::PairDesc*)(base + lay.pairs);
+  L.num_pairs = (int)pairs.size();
+  L.W = pl.W;
+  L.TR = pl.TR;
+  L.TC = pl.TC;
+  L.num_teams = num_teams;
+  L.max_N = maxN;
+  L.xbuf = (uint64_t*)(base + lay.xbuf);
+  L.xbuf_stride = lay.xbuf_stride;
+  L.wsT = (float*)(base + lay.wsT);
+  L.wsT_stride = lay.wsT_stride;
+  L.wsY = (float*)(base + lay.wsY);
+  L.wsY_stride = lay.wsY_stride;
+  L.queue = (unsigned*)(base + lay.queue);
+  L.timeout_ticks = 100000000LL * 20;  // 20 s of the 100 MHz wall clock
+
+  HIPCHK(h, hipMemcpyAsync(base + lay.pairs, pd.data(),
+                           sizeof(fpfp::PairDesc) * pd.size(),
+                           hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemsetAsync(base + lay.queue, 0, 16, h->stream));
+  HIPCHK(h, hipMemsetAsync(base + lay.infos, 0,
+                           sizeof(fpfp::DevInfo) * pd.size(), h->stream));
+  HIPCHK(h, hipMemsetAsync(base + lay.xbuf, 0,
+                           sizeof(uint64_t) * lay.xbuf_stride * num_teams,
+                           h->stream));
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  HIPCHK(h, fpfp_launch_persistent(&L, G, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  std::vector<fpfp::DevInfo> di(pd.size());
+  unsigned q2[2] = {0, 0};
+  std::vector<float> tr(want_trace ? max_outer : 0);
+  HIPCHK(h, hipMemcpyAsync(di.data(), base + lay.infos,
+                           sizeof(fpfp::DevInfo) * di.size(),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(q2, base + lay.queue, sizeof q2,
+                           hipMemcpyDeviceToHost, h->stream));
+  if (want_trace)
+    HIPCHK(h, hipMemcpyAsync(tr.data(), base + lay.trace,
+                             sizeof(float) * tr.size(), hipMemcpyDeviceToHost,
+                             h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (q2[1] != 0)
+    return fail(h, FASTPFP_ERR_TIMEOUT,
+                "a device-side wait exceeded its limit; results are invalid");
+  fastpfp_status first = FASTPFP_OK;
+  for (size_t b = 0; b < di.size(); ++b) {
+    fastpfp_info& o = infos[b];
+    o.outer_iters = di[b].outer;
+    o.inner_iters_total = di[b].inner_total;
+    o.inner_iters_max = di[b].inner_max;
+    o.inner_capped = di[b].inner_capped;
+    o.converged = di[b].converged;
+    o.status = di[b].status;
+    o.eps1_last = di[b].eps1;
+    o.eps2_last = di[b].eps2;
+    o.kernel_ms = ms;
+    if (o.status != 0 && first == FASTPFP_OK) first = (fastpfp_status)o.status;
+  }
+  if (want_trace) {
+    h->trace.assign(tr.begin(), tr.begin() + std::min<int>(di[0].outer, max_outer));
+  }
+  if (first != FASTPFP_OK)
+    return fail(h, first, "non-finite values met during the solve");
+  return FASTPFP_OK;
+}
+
+bool bad_ld(int ld, int cols) { return ld < cols; }
+
+}  // namespace
+
+extern "C" {
+
+int fastpfp_abi_version(void) { return FASTPFP_ABI_VERSION; }
+
+const char* fastpfp_status_string(fastpfp_status s) {
+  switch (s) {
+    case FASTPFP_OK: return "ok";
+    case FASTPFP_ERR_INVALID_ARG: return "invalid argument";
+    case FASTPFP_ERR_SHAPE: return "shape out of range";
+    case FASTPFP_ERR_HIP: return "HIP runtime error";
+    case FASTPFP_ERR_NOMEM: return "out of device memory";
+    case FASTPFP_ERR_NUMERIC: return "non-finite values";
+    case FASTPFP_ERR_TIMEOUT: return "device wait timed out";
+    case FASTPFP_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char* fastpfp_last_error(fastpfp_t h) {
+  return h ? h->err.c_str() : "NULL handle";
+}
+
+fastpfp_status fastpfp_params_default(fastpfp_params* p) {
+  if (!p) return FASTPFP_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof *p);
+  p->lambda = 0.0;
+  p->alpha = 0.5;
+  p->tol_outer = 1e-6;
+  p->tol_inner = 1e-8;
+  p->max_outer = 1000;
+  p->max_inner = 1000;
+  p->precision = FASTPFP_FP32;
+  p->init = FASTPFP_INIT_UNIFORM;
+  p->init_scale = 0.0;
+  p->normalize_max = 1;
+  p->team_size = 0;
+  return FASTPFP_OK;
+}
+
+fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
+                              int max_np, void* hip_stream) {
+  if (!out) return FASTPFP_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (max_n < 1 || max_np < 1) return FASTPFP_ERR_SHAPE;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return FASTPFP_ERR_HIP;
+  fastpfp_ctx* h = new fastpfp_ctx;
+  h->device = device;
+  h->max_n = max_n;
+  h->max_np = max_np;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount,
+                            device) != hipSuccess ||
+      fpfp_occupancy(&h->occupancy) != hipSuccess ||
+      hipEventCreate(&h->ev0) != hipSuccess ||
+      hipEventCreate(&h->ev1) != hipSuccess) {
+    delete h;
+    return FASTPFP_ERR_HIP;
+  }
+  *out = h;
+  return FASTPFP_OK;
+}
+
+fastpfp_status fastpfp_destroy(fastpfp_t h) {
+  if (!h) return FASTPFP_ERR_INVALID_ARG;
+  hipSetDevice(h->device);
+  if (h->ws) hipFree(h->ws);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+  return FASTPFP_OK;
+}
+
+fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np, const float* A,
+                             int lda, const float* B, int ldb, const float* K,
+                             int ldk, const fastpfp_params* p, float* X,
+                             int ldx, float* Y_state, fastpfp_info* info) {
+  if (!h) return FASTPFP_ERR_INVALID_ARG;
+  fastpfp_status st = check_params(h, p);
+  if (st != FASTPFP_OK) return st;
+  if (n < 1 || np < 1 || n > h->max_n || np > h->max_np)
+    return fail(h, FASTPFP_ERR_SHAPE, "n=%d n'=%d outside [1, %d] x [1, %d]",
+                n, np, h->max_n, h->max_np);
+  if (!A || !B || !X)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "A, B and X must be non-NULL");
+  if (p->lambda > 0.0 && !K)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "K is NULL but lambda > 0");
+  if (bad_ld(lda, n) || bad_ld(ldb, np) || bad_ld(ldx, np) ||
+      (p->lambda > 0.0 && bad_ld(ldk, np)))
+    return fail(h, FASTPFP_ERR_SHAPE, "a leading dimension is too small");
+  std::vector<PairIn> pairs(1);
+  pairs[0] = PairIn{n, np, A, B, K, X, Y_state, lda, ldb, ldk, ldx};
+  fastpfp_info tmp;
+  std::memset(&tmp, 0, sizeof tmp);
+  st = run(h, pairs, p, fpfp::kModeSolve, p->max_inner, p->tol_inner,
+           p->team_size, true, &tmp);
+  if (info) *info = tmp;
+  return st;
+}
+
+fastpfp_status fastpfp_solve_batched(fastpfp_t h, int batch, const int* n_host,
+                                     const int* np_host, const float* A,
+                                     const int64_t* offA_host, const float* B,
+                                     const int64_t* offB_host, const float* K,
+                                     const int64_t* offK_host,
+                                     const fastpfp_params* p, float* X,
+                                     const int64_t* offX_host,
+                                     fastpfp_info* infos_host) {
+  if (!h) return FASTPFP_ERR_INVALID_ARG;
+  fastpfp_status st = check_params(h, p);
+  if (st != FASTPFP_OK) return st;
+  if (batch < 1 || !n_host || !np_host || !A || !offA_host || !B ||
+      !offB_host || !X || !offX_host)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "NULL batch argument");
+  if (p->lambda > 0.0 && (!K || !offK_host))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "K is NULL but lambda > 0");
+  std::vector<PairIn> pairs(batch);
+  for (int b = 0; b < batch; ++b) {
+    const int n = n_host[b], np = np_host[b];
+    if (n < 1 || np < 1 || n > h->max_n || np > h->max_np)
+      return fail(h, FASTPFP_ERR_SHAPE, "pair %d: n=%d n'=%d out of range", b,
+                  n, np);
+    if (offA_host[b] < 0 || offB_host[b] < 0 || offX_host[b] < 0 ||
+        (p->lambda > 0.0 && offK_host[b] < 0))
+      return fail(h, FASTPFP_ERR_INVALID_ARG, "pair %d: negative offset", b);
+    pairs[b] = PairIn{n,
+                      np,
+                      A + offA_host[b],
+                      B + offB_host[b],
+                      (p->lambda > 0.0) ? K + offK_host[b] : nullptr,
+                      X + offX_host[b],
+                      nullptr,
+                      n,
+                      np,
+                      np,
+                      np};
+  }
+  std::vector<fastpfp_info> tmp(batch);
+  st = run(h, pairs, p, fpfp::kModeSolve, p->max_inner, p->tol_inner,
+           p->team_size, false, tmp.data());
+  if (infos_host) std::memcpy(infos_host, tmp.data(), sizeof(fastpfp_info) * batch);
+  return st;
+}
+
+fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
+                               int max_inner, int team_size,
+                               fastpfp_info* info) {
+  if (!h) return FASTPFP_ERR_INVALID_ARG;
+  if (N < 1 || N > std::max(h->max_n, h->max_np))
+    return fail(h, FASTPFP_ERR_SHAPE, "N=%d out of range", N);
+  if (!Y) return fail(h, FASTPFP_ERR_INVALID_ARG, "Y is NULL");
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_inner < 1 || team_size < 0)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "bad tolerance, cap or team size");
+  std::vector<PairIn> pairs(1);
+  pairs[0] = PairIn{N, N, nullptr, nullptr, nullptr, nullptr, Y, N, N, N, N};
+  fastpfp_info tmp;
+  std::memset(&tmp, 0, sizeof tmp);
+  fastpfp_status st = run(h, pairs, nullptr, fpfp::kModeProject, max_inner,
+                          tol, team_size, false, &tmp);
+  if (info) *info = tmp;
+  return st;
+}
+
+fastpfp_status fastpfp_get_trace(fastpfp_t h, double* out_host, int cap,
+                                 int* count) {
+  if (!h || !count || (cap > 0 && !out_host)) return FASTPFP_ERR_INVALID_ARG;
+  const int m = std::min<int>(cap, (int)h->trace.size());
+  for (int i = 0; i < m; ++i) out_host[i] = h->trace[i];
+  *count = m;
+  return FASTPFP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Structures shared by the host API (fastpfp_api.cpp) and the device code
+// (fastpfp_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace fpfp {
+
+// Threads per workgroup and the register tile of the projection phase: each
+// thread keeps kRA x kCB entries of Y, so one workgroup's tile of the slacked
+// matrix is at most kTileRows x kTileCols.
+constexpr int kThreads = 256;
+constexpr int kRA = 8;
+constexpr int kCB = 16;
+constexpr int kTileRows = 16 * kRA;  // 128
+constexpr int kTileCols = 16 * kCB;  // 256
+constexpr int kScal = 4;             // scalars each workgroup posts per exchange
+constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies
+constexpr int kMaxTeamSide = 16;     // tile rows / columns per team, each
+
+enum PairMode { kModeSolve = 0, kModeProject = 1 };
+
+struct DevInfo {
+  int outer, inner_total, inner_max, inner_capped, converged, status;
+  float eps1, eps2;
+};
+
+// One matching problem as the persistent kernel sees it.
+struct PairDesc {
+  const float* A;  // n x n, row pitch lda
+  const float* B;  // np x np, row pitch ldb
+  const float* K;  // n x np, row pitch ldk, or null when lam == 0
+  float* X;        // n x np, row pitch ldx: X0 in, final X out
+  float* Y;        // N x N state (row pitch N); null -> team workspace
+  float* trace;    // eps1 per outer step (max_outer floats) or null
+  DevInfo* info;
+  int n, np, N, lda, ldb, ldk, ldx;
+  int mode, init_user, y_user, normalize, max_outer, max_inner, precision;
+  float lam, alpha, tol_out, tol_in, init_c;
+};
+
+// One persistent launch: teams of W workgroups, each team a TR x TC grid of
+// projection tiles, pulling pairs from a shared queue.
+struct LaunchDesc {
+  const PairDesc* pairs;
+  int num_pairs;
+  int W, TR, TC, num_teams;
+  int max_N;                  // largest N in the launch (workspace sizing)
+  uint64_t* xbuf;             // exchange words, per team
+  long long xbuf_stride;      // u64 words per team
+  float* wsT;                 // per team: T^T scratch (max np x n)
+  long long wsT_stride;
+  float* wsY;                 // per team: slacked Y (max N x N)
+  long long wsY_stride;
+  unsigned* queue;            // [0]: next pair; [1]: abort flag
+  long long timeout_ticks;    // wall-clock ticks a wait may last
+};
+
+// Exchange layout for one team and one parity buffer (u64 words):
+//   rowp[TC][NPR], colp[TR][NPC], scal[W][kScal]
+__host__ __device__ inline long long xbuf_words_per_parity(int TR, int TC,
+                                                          int W, int maxN) {
+  long long h = (maxN + TR - 1) / TR, w = (maxN + TC - 1) / TC;
+  return (long long)TC * (TR * h) + (long long)TR * (TC * w) +
+         (long long)W * kScal;
+}
+
+}  // namespace fpfp

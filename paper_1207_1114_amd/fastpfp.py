@@ -1,0 +1,232 @@
+"""Python binding of libfastpfp.so (the C ABI declared in include/fastpfp.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and the HIP stream.  The
+library must be built first (``python -m paper_1207_1114_amd.build``); if it
+is missing, importing this module raises, so nothing silently falls back to a
+CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "libfastpfp.so")
+
+FP32, BF16 = 0, 1
+INIT_UNIFORM, INIT_USER = 0, 1
+HUNGARIAN, GREEDY = 0, 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
+          3: "HIP runtime error", 4: "out of device memory",
+          5: "non-finite values", 6: "device wait timed out",
+          7: "unsupported request"}
+
+EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
+           "fastpfp_solve", "fastpfp_solve_batched", "fastpfp_project",
+           "fastpfp_discretize", "fastpfp_get_trace", "fastpfp_status_string",
+           "fastpfp_last_error", "fastpfp_abi_version")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("tol_outer", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("precision", ctypes.c_int), ("init", ctypes.c_int),
+                ("init_scale", ctypes.c_double),
+                ("normalize_max", ctypes.c_int), ("team_size", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int),
+                ("inner_iters_total", ctypes.c_int),
+                ("inner_iters_max", ctypes.c_int),
+                ("inner_capped", ctypes.c_int), ("converged", ctypes.c_int),
+                ("status", ctypes.c_int), ("eps1_last", ctypes.c_double),
+                ("eps2_last", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FastPFPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing; build it with "
+            "`python -m paper_1207_1114_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I, L = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER
+    lib.fastpfp_params_default.argtypes = [L(Params)]
+    lib.fastpfp_create.argtypes = [L(P), I, I, I, P]
+    lib.fastpfp_destroy.argtypes = [P]
+    lib.fastpfp_solve.argtypes = [P, I, I, P, I, P, I, P, I, L(Params), P, I,
+                                  P, L(Info)]
+    lib.fastpfp_solve_batched.argtypes = [P, I, P, P, P, P, P, P, P, P,
+                                          L(Params), P, P, P]
+    lib.fastpfp_project.argtypes = [P, I, P, ctypes.c_double, I, I, L(Info)]
+    lib.fastpfp_discretize.argtypes = [I, I, P, I, I, P, L(ctypes.c_double)]
+    lib.fastpfp_get_trace.argtypes = [P, P, I, L(I)]
+    lib.fastpfp_status_string.argtypes = [I]
+    lib.fastpfp_status_string.restype = ctypes.c_char_p
+    lib.fastpfp_last_error.argtypes = [P]
+    lib.fastpfp_last_error.restype = ctypes.c_char_p
+    for name in ("fastpfp_params_default", "fastpfp_create",
+                 "fastpfp_destroy", "fastpfp_solve", "fastpfp_solve_batched",
+                 "fastpfp_project", "fastpfp_discretize",
+                 "fastpfp_get_trace", "fastpfp_abi_version"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().fastpfp_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, "lambda_" if k in ("lam", "lambda") else k, v)
+    return p
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _check_dev(t, name):
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major matrix")
+
+
+class Solver:
+    """A library handle bound to one device and one stream."""
+
+    def __init__(self, max_n: int, max_np: int, device: int = 0,
+                 stream=None):
+        import torch
+        self._lib = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self._lib.fastpfp_create(ctypes.byref(h), device, max_n, max_np,
+                                      ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise FastPFPError(st, "fastpfp_create failed")
+        self._h = h
+        self.max_n, self.max_np, self.device = max_n, max_np, device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fastpfp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        raise FastPFPError(st, self._lib.fastpfp_last_error(self._h)
+                           .decode(errors="replace"))
+
+    def solve(self, A, B, K, X, params: Params, Y_state=None) -> dict:
+        """In-place solve of one pair; X holds X0 (INIT_USER) and the result."""
+        for t, nm in ((A, "A"), (B, "B"), (K, "K"), (X, "X"),
+                      (Y_state, "Y_state")):
+            _check_dev(t, nm)
+        n, np_ = A.shape[0], B.shape[0]
+        info = Info()
+        st = self._lib.fastpfp_solve(
+            self._h, n, np_, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+            _ptr(K), K.stride(0) if K is not None else 0,
+            ctypes.byref(params), _ptr(X), X.stride(0), _ptr(Y_state),
+            ctypes.byref(info))
+        if st != 0:
+            self._raise(st)
+        return info.as_dict()
+
+    def solve_batched(self, n: Sequence[int], np_: Sequence[int], A, offA,
+                      B, offB, K, offK, X, offX, params: Params) -> list:
+        """Packed ragged batch: A, B, K, X are flat float32 device tensors;
+        off* are element offsets (host sequences)."""
+        b = len(n)
+        ni = np.asarray(n, dtype=np.int32)
+        npi = np.asarray(np_, dtype=np.int32)
+        oa, ob, ox = (np.asarray(o, dtype=np.int64) for o in (offA, offB, offX))
+        ok = np.asarray(offK if offK is not None else np.zeros(b),
+                        dtype=np.int64)
+        infos = (Info * b)()
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        st = self._lib.fastpfp_solve_batched(
+            self._h, b, c(ni), c(npi), _ptr(A), c(oa), _ptr(B), c(ob),
+            _ptr(K), c(ok), ctypes.byref(params), _ptr(X), c(ox), infos)
+        out = [i.as_dict() for i in infos]
+        if st != 0:
+            err = FastPFPError(st, self._lib.fastpfp_last_error(self._h)
+                               .decode(errors="replace"))
+            err.infos = out
+            raise err
+        return out
+
+    def project(self, Y, tol: float, max_inner: int, team_size: int = 0
+                ) -> dict:
+        _check_dev(Y, "Y")
+        info = Info()
+        st = self._lib.fastpfp_project(self._h, Y.shape[0], _ptr(Y), tol,
+                                       max_inner, team_size,
+                                       ctypes.byref(info))
+        if st != 0:
+            self._raise(st)
+        return info.as_dict()
+
+    def trace(self, cap: int = 100000) -> np.ndarray:
+        out = np.zeros(cap, dtype=np.float64)
+        cnt = ctypes.c_int()
+        self._lib.fastpfp_get_trace(self._h,
+                                    out.ctypes.data_as(ctypes.c_void_p), cap,
+                                    ctypes.byref(cnt))
+        return out[:cnt.value].copy()
+
+
+def discretize(X: np.ndarray, method: int = HUNGARIAN) -> tuple:
+    """Host discretisation (Sec. 4.5).  Returns (match int32[n], score)."""
+    Xc = np.ascontiguousarray(X, dtype=np.float32)
+    n, m = Xc.shape
+    match = np.zeros(n, dtype=np.int32)
+    score = ctypes.c_double()
+    st = lib().fastpfp_discretize(n, m, Xc.ctypes.data_as(ctypes.c_void_p),
+                                  m, method,
+                                  match.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(score))
+    if st != 0:
+        raise FastPFPError(st, "fastpfp_discretize failed")
+    return match, score.value

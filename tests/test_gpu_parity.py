@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
+
+Tolerances.  The GPU computes in float32.  One projection pass rounds each
+entry a few times (relative error ~1e-7); over the T passes compared here the
+error grows at most linearly and is damped by the projection's
+non-expansiveness, so every projection comparison uses
+|Y_gpu - Y_ref| <= 1e-4 * max|Y_ref|, and every solve uses the target bound
+|X_gpu - X_ref| <= 1e-4 * max|X_ref| (max X = 1 after step 9) plus an identical
+Hungarian matching.  Integer results (iteration counts, matchings) compare
+exactly, except where a float32 value sits on a stopping threshold (noted).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fastpfp_oracle as O
+from paper_1207_1114_amd import synth
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1207_1114_amd import fastpfp as F
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    S = F.Solver(4096, 4096)
+    return torch, F, S
+
+
+def dev(torch, a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda:0")
+
+
+def gpu_solve(env, p, prm=None, X0=None, Y0=None, **kw):
+    torch, F, S = env
+    prm = prm or F.default_params(**kw)
+    A, B = dev(torch, p.A), dev(torch, p.B)
+    K = dev(torch, p.K) if (p.K is not None and prm.lambda_ > 0) else None
+    X = dev(torch, X0) if X0 is not None else torch.zeros(
+        p.n, p.np_, device="cuda:0")
+    Y = dev(torch, Y0) if Y0 is not None else None
+    info = S.solve(A, B, K, X, prm, Y_state=Y)
+    return X.cpu().numpy().astype(np.float64), info, (
+        Y.cpu().numpy().astype(np.float64) if Y is not None else None)
+
+
+# ------------------------------------------------------------ projection
+@pytest.mark.parametrize("N,T,team", [(1, 5, 0), (2, 40, 0), (17, 120, 0),
+                                      (129, 60, 0), (257, 40, 0),
+                                      (300, 40, 0), (300, 40, 16),
+                                      (513, 30, 0), (1000, 20, 0),
+                                      (1000, 20, 64)])
+def test_projection_parity(env, N, T, team):
+    torch, F, S = env
+    rng = np.random.default_rng([N, T])
+    Y = rng.normal(size=(N, N)) * 2.0 + 0.5
+    Yg = dev(torch, Y)
+    info = S.project(Yg, 1e-30, T, team)
+    ref = O.inner_projection(Y, 1e-30, T)
+    got = Yg.cpu().numpy()
+    scale = max(1.0, np.abs(ref.Y).max())
+    assert np.abs(got - ref.Y).max() <= 1e-4 * scale
+    assert np.all(got >= 0)
+    # both stop early only on an exact fixed point (max|dY| = 0 < 1e-30);
+    # float32 may reach one before float64 does
+    it = info["inner_iters_total"]
+    assert it == ref.iters or (it < ref.iters and info["eps2_last"] == 0.0)
+
+
+def test_projection_n1_and_stopping_rule(env):
+    torch, F, S = env
+    Y = dev(torch, [[3.5]])
+    info = S.project(Y, 1e-12, 100)
+    assert Y.item() == 1.0 and info["inner_iters_total"] == 2
+    # N = 2 clamped case of the closed form: excess halves every pass
+    Y2 = dev(torch, [[3.0, -1.0], [0.5, 2.5]])
+    info = S.project(Y2, 1e-6, 10_000)
+    ref = O.inner_projection(np.array([[3.0, -1.0], [0.5, 2.5]]), 1e-6, 10_000)
+    assert info["inner_iters_total"] == ref.iters
+    np.testing.assert_allclose(Y2.cpu().numpy(), ref.Y, atol=1e-6)
+
+
+# ----------------------------------------------------------------- solves
+def assert_solve_parity(p, X, info, ref):
+    assert np.abs(X - ref.X).max() <= 1e-4 * np.abs(ref.X).max()
+    assert info["outer_iters"] == ref.outer_iters
+    np.testing.assert_array_equal(O.hungarian_discretize(X),
+                                  O.hungarian_discretize(ref.X))
+
+
+def test_solve_config0_parity(env):
+    p = synth.config0_pair(0)
+    X, info, _ = gpu_solve(env, p)
+    ref = O.fastpfp(p.A, p.B, p.K, p.lam)
+    assert info["converged"] == 1 and ref.converged
+    assert_solve_parity(p, X, info, ref)
+    assert O.accuracy(O.hungarian_discretize(X), p.perm) == 1.0
+
+
+@pytest.mark.parametrize("n,m", [(60, 75), (75, 60), (130, 140)])
+def test_solve_unequal_sizes_with_similarity(env, n, m):
+    rng = synth.rng_for(99, n * 1000 + m)
+    A = synth.random_weighted_graph(rng, n, 0.2)
+    B = synth.random_weighted_graph(rng, m, 0.2)
+    K = rng.random((n, m))
+    p = synth.GraphPair(A, B, K, 0.7, np.full(n, -1))
+    kw = dict(max_outer=6, max_inner=150)
+    X, info, _ = gpu_solve(env, p, lambda_=0.7, **kw)
+    ref = O.fastpfp(A, B, K, 0.7, **kw)
+    assert_solve_parity(p, X, info, ref)
+    # an inner loop whose float64 max|dY| lands within rounding of eps2 may
+    # stop one pass earlier or later in float32: at most one per outer step
+    assert abs(info["inner_iters_total"] - sum(ref.inner_iters)) <= \
+        ref.outer_iters
+
+
+def test_solve_config2_small_outliers(env):
+    p = synth.config2_pair(3, n=90, n_out=18)
+    X, info, _ = gpu_solve(env, p, lambda_=p.lam, max_inner=300)
+    ref = O.fastpfp(p.A, p.B, p.K, p.lam, max_inner=300)
+    assert_solve_parity(p, X, info, ref)
+    # rows (smaller side) sum to ~1, columns to <= 1 before normalisation;
+    # after step 9 the iterate is a positive multiple of such a matrix
+    assert np.all(X >= 0) and X.max() == 1.0
+
+
+def test_solve_config1_full_size_against_stored_oracle(env):
+    torch, F, S = env
+    g = np.load(os.path.join(GOLD, "config1_pair0.npz"))
+    p = synth.config1_pair(0)
+    X, info, _ = gpu_solve(env, p, lambda_=p.lam)
+    tr = S.trace()
+    ref_tr = g["eps1"]
+    print("eps1 gpu   ", " ".join(f"{v:.3e}" for v in tr))
+    print("eps1 oracle", " ".join(f"{v:.3e}" for v in ref_tr))
+    # Entries near 1 carry float32 rounding from ~1000 passes per step
+    # (random walk of ulp(1) = 1.2e-7: a few 1e-6), and eps1 is a max of
+    # differences of such entries, so it agrees to 2 x 5e-6 = 1e-5; the stop
+    # (eps1 < 1e-6) may then fall one step later or earlier.
+    k = min(len(tr), len(ref_tr))
+    assert np.all(np.abs(tr[:k] - ref_tr[:k]) <= 1e-5 + 1e-3 * ref_tr[:k])
+    assert abs(info["outer_iters"] - int(g["outer"])) <= 1
+    got = X[g["rows"], g["cols"]]
+    assert np.abs(got - g["xs"]).max() <= 1e-4 * float(g["xmax"])
+    np.testing.assert_array_equal(O.hungarian_discretize(X), g["match"])
+    # unsampled entries: row / column sums of the whole iterate
+    np.testing.assert_allclose(X.sum(1), g["xsum_rows"], atol=1e-3)
+    np.testing.assert_allclose(X.sum(0), g["xsum_cols"], atol=1e-3)
+
+
+def test_resume_from_state_equals_uninterrupted(env):
+    torch, F, S = env
+    p = synth.config2_pair(1, n=40, n_out=9)
+    N = p.np_
+    kw = dict(lambda_=p.lam, max_inner=120, tol_outer=1e-30)
+    Xa, ia, _ = gpu_solve(env, p, max_outer=6, **kw)
+    Xh, ih, Yh = gpu_solve(env, p, max_outer=3, Y0=np.zeros((N, N)), **kw)
+    prm = F.default_params(max_outer=3, init=F.INIT_USER, **kw)
+    Xb, ib, _ = gpu_solve(env, p, prm=prm, X0=Xh, Y0=Yh)
+    np.testing.assert_array_equal(Xa, Xb)
+
+
+def test_repeatable_bitwise(env):
+    p = synth.config0_pair(1, n=150)
+    X1, i1, _ = gpu_solve(env, p, max_outer=5)
+    X2, i2, _ = gpu_solve(env, p, max_outer=5)
+    np.testing.assert_array_equal(X1, X2)
+    assert i1["inner_iters_total"] == i2["inner_iters_total"]
+
+
+def test_non_finite_input_reports_numeric(env):
+    torch, F, S = env
+    p = synth.config0_pair(2, n=30)
+    A = p.A.copy()
+    A[3, 4] = A[4, 3] = np.nan
+    q = synth.GraphPair(A, p.B, None, 0.0, p.perm)
+    with pytest.raises(F.FastPFPError) as e:
+        gpu_solve(env, q, max_outer=3)
+    assert e.value.status == 5
+
+
+def test_invalid_arguments_are_rejected(env):
+    torch, F, S = env
+    p = synth.config0_pair(0, n=8)
+    for kw in (dict(alpha=0.0), dict(alpha=1.5), dict(tol_inner=0.0),
+               dict(max_outer=0), dict(lambda_=-1.0)):
+        with pytest.raises(F.FastPFPError) as e:
+            gpu_solve(env, p, **kw)
+        assert e.value.status == 1
+    with pytest.raises(F.FastPFPError) as e:    # lambda > 0 without K
+        gpu_solve(env, p, lambda_=1.0)
+    assert e.value.status == 1
+    with pytest.raises(F.FastPFPError) as e:    # beyond the handle bound
+        S.project(dev(torch, np.zeros((4097, 1))), 1e-6, 3)
+    assert e.value.status == 2
+
+
+# ---------------------------------------------------------------- batches
+def pack(pairs):
+    offs = {k: [] for k in "ABKX"}
+    bufs = {k: [] for k in "ABKX"}
+    cur = {k: 0 for k in "ABKX"}
+    for p in pairs:
+        mats = dict(A=p.A, B=p.B, K=p.K, X=np.zeros((p.n, p.np_)))
+        for k, mtx in mats.items():
+            offs[k].append(cur[k])
+            bufs[k].append(mtx.ravel())
+            cur[k] += mtx.size
+    return {k: np.concatenate(v) for k, v in bufs.items()}, offs
+
+
+def test_batched_equals_single_solves(env):
+    torch, F, S = env
+    pairs = [synth.config3_pair(i) for i in range(6)]
+    pairs += [synth.config3_pair(100, n=50, n_extra=0),
+              synth.config3_pair(101, n=400, n_extra=40)]
+    team = 16
+    prm = F.default_params(lambda_=1.0, max_outer=8, max_inner=200,
+                           team_size=team)
+    bufs, offs = pack(pairs)
+    d = {k: dev(torch, v).view(-1, 1) for k, v in bufs.items()}
+    infos = S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                            d["A"], offs["A"], d["B"], offs["B"], d["K"],
+                            offs["K"], d["X"], offs["X"], prm)
+    Xall = d["X"].cpu().numpy().ravel()
+    for p, o, inf in zip(pairs, offs["X"], infos):
+        Xb = Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
+        Xs, info, _ = gpu_solve(env, p, prm=prm)
+        np.testing.assert_array_equal(Xb, Xs)
+        assert inf["outer_iters"] == info["outer_iters"]
+        assert inf["inner_iters_total"] == info["inner_iters_total"]
