@@ -149,7 +149,7 @@ Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
 fastpfp_status ensure_ws(fastpfp_t h, size_t bytes) {
   if (bytes <= h->ws_bytes) return FASTPFP_OK;
   if (h->ws) {
-    hipFree(h->ws);
+    (void)hipFree(h->ws);
     h->ws = nullptr;
     h->ws_bytes = 0;
   }
@@ -248,6 +248,7 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   L.TC = pl.TC;
   L.num_teams = num_teams;
   L.max_N = maxN;
+  L.cus_per_xcd = std::max(1, h->cu_count / fpfp::kXcds);
   L.xbuf = (uint64_t*)(base + lay.xbuf);
   L.xbuf_stride = lay.xbuf_stride;
   L.wsT = (float*)(base + lay.wsT);
@@ -380,10 +381,10 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
 
 fastpfp_status fastpfp_destroy(fastpfp_t h) {
   if (!h) return FASTPFP_ERR_INVALID_ARG;
-  hipSetDevice(h->device);
-  if (h->ws) hipFree(h->ws);
-  if (h->ev0) hipEventDestroy(h->ev0);
-  if (h->ev1) hipEventDestroy(h->ev1);
+  (void)hipSetDevice(h->device);
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;
   return FASTPFP_OK;
 }

@@ -5,17 +5,21 @@
 
 namespace fpfp {
 
-// Threads per workgroup and the register tile of the projection phase: each
-// thread keeps kRA x kCB entries of Y, so one workgroup's tile of the slacked
-// matrix is at most kTileRows x kTileCols.
+// Threads per workgroup and the projection tile: thread (pr, pc) of the
+// 16 x 16 thread grid owns tile rows pr + 16a (a < kRA) and columns
+// pc + 16b (b < kCB); rows a < kRegRows live in registers, the others in
+// LDS.  One workgroup's tile of the slacked matrix is at most
+// kTileRows x kTileCols.
 constexpr int kThreads = 256;
-constexpr int kRA = 8;
+constexpr int kRA = 16;
 constexpr int kCB = 16;
-constexpr int kTileRows = 16 * kRA;  // 128
+constexpr int kRegRows = 8;
+constexpr int kTileRows = 16 * kRA;  // 256
 constexpr int kTileCols = 16 * kCB;  // 256
 constexpr int kScal = 4;             // scalars each workgroup posts per exchange
 constexpr int kXcds = 8;             // MI355X: 8 accelerator complex dies
 constexpr int kMaxTeamSide = 16;     // tile rows / columns per team, each
+constexpr int kMaxTeam = kMaxTeamSide * kMaxTeamSide;
 
 enum PairMode { kModeSolve = 0, kModeProject = 1 };
 
@@ -45,6 +49,7 @@ struct LaunchDesc {
   int num_pairs;
   int W, TR, TC, num_teams;
   int max_N;                  // largest N in the launch (workspace sizing)
+  int cus_per_xcd;            // compute units per XCD (team placement)
   uint64_t* xbuf;             // exchange words, per team
   long long xbuf_stride;      // u64 words per team
   float* wsT;                 // per team: T^T scratch (max np x n)

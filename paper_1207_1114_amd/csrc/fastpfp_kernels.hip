@@ -16,13 +16,15 @@
 // Y + (1/N + s/N^2 - r/N) 1^T - 1 (c/N)^T, evaluated without forming the
 // large cancelling terms r_i/N and s/N^2 separately.
 //
-// The team owns the slacked N x N matrix Y as a TR x TC grid of tiles, one per
-// workgroup, held in registers for the whole inner loop.  Each inner pass is
-// one team-wide exchange of tile row sums, column sums, tile totals and
-// max|dY|: every word carries the exchange's sequence number in its high
-// half, so the data itself is the signal and no separate barrier or fence is
-// needed.  Bulk data (T, Y, X) crosses workgroups through global memory with
-// agent-scope release/acquire fences around an exchange.
+// The team owns the slacked N x N matrix Y as a TR x TC grid of tiles of at
+// most 256 x 256, one per workgroup (one workgroup per compute unit).  A tile
+// stays on chip for the whole inner loop: half of each thread's 256 entries
+// in registers, half in LDS.  Each inner pass is one team-wide exchange of
+// tile row sums, column sums, tile totals and max|dY|: every 64-bit word
+// carries the exchange's sequence number in its high half, so the data itself
+// is the signal and no separate barrier or fence is needed.  Bulk data (T, Y,
+// X) crosses workgroups through global memory with agent-scope
+// release/acquire fences around an exchange.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -33,6 +35,8 @@
 namespace fpfp {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kLdsRows = kRA - kRegRows;  // tile rows per thread held in LDS
 
 // ------------------------------------------------------------ exchange words
 __device__ __forceinline__ uint64_t pack(unsigned seq, float v) {
@@ -51,7 +55,7 @@ __device__ __forceinline__ uint64_t get_word(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Per-workgroup view of its team and of the launch.
+// Per-workgroup view of its team.
 struct Team {
   int team, rank, W, TR, TC, tr, tc;
   uint64_t* xb;        // this team's exchange words (both parities)
@@ -62,18 +66,23 @@ struct Team {
 };
 
 struct Shared {
-  // GEMM staging
-  float lp[32][64];
-  float lq[32][64];
-  // projection reductions
-  float rowred[kTileRows];
-  float colred[4][kTileCols];
+  // LDS-resident part of the tile: entry (a, b) of thread t at
+  // ly[(a - kRegRows) * kCB + b][t] (consecutive threads, consecutive banks)
+  float ly[kLdsRows * kCB][kThreads];
+  union {
+    struct {  // GEMM operand staging
+      float lp[32][64];
+      float lq[32][64];
+    } g;
+    float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
+  } u;
+  float lrow[kTileRows];
   float a_l[kTileRows];
   float b_l[kTileCols];
-  float scal[512][kScal];
+  float scal[kMaxTeam][kScal];
   float wred[4];
-  double dred[4];
-  int bad;
+  double dred[3];
+  double dtile[4];
 };
 
 // Value the compiler cannot see through: recomputed wherever it is used, so
@@ -84,79 +93,108 @@ __device__ __forceinline__ int opaque(int x) {
   return x;
 }
 
-// Waits until the `n` (<= M) words base[k * stride] all carry tag `seq` and
-// returns their payloads in out[].  Returns false when the launch is aborted
-// or the wait outlives the timeout.
-template <int M>
-__device__ __forceinline__ bool gather(const uint64_t* base, long long stride,
-                                       int n, unsigned seq, float (&out)[M],
-                                       const Team& tm) {
-  uint64_t v[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) v[k] = (k < n) ? get_word(base + k * stride) : 0;
-  int spins = 0;
-  long long t0 = 0;
-  for (;;) {
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < M; ++k) ok &= (k >= n) || (tag_of(v[k]) == seq);
-    if (ok) break;
-    if ((++spins & 63) == 0) {
-      if (__hip_atomic_load(tm.abort_flag, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT) != 0u)
-        return false;
-      const long long now = (long long)wall_clock64();
-      if (t0 == 0) t0 = now;
-      if (now - t0 > tm.timeout) {
-        __hip_atomic_store(tm.abort_flag, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (int k = 0; k < M; ++k)
-      if (k < n && tag_of(v[k]) != seq) v[k] = get_word(base + k * stride);
+__device__ __forceinline__ bool timed_out(const Team& tm, long long& t0) {
+  if (__hip_atomic_load(tm.abort_flag, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT) != 0u)
+    return true;
+  const long long now = (long long)wall_clock64();
+  if (t0 == 0) t0 = now;
+  if (now - t0 > tm.timeout) {
+    __hip_atomic_store(tm.abort_flag, 1u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return true;
   }
-#pragma unroll
-  for (int k = 0; k < M; ++k) out[k] = unpack(v[k]);
-  return true;
+  return false;
 }
 
-// Workgroup-uniform failure flag: true if any thread failed.
-__device__ __forceinline__ bool wg_any(Shared& sh, bool fail) {
-  return __syncthreads_or(fail) != 0;
+// Gathers three strided runs of exchange words -- nr (<= 8) words at
+// base_r + k*str_r, nc (<= 8) at base_c + k*str_c and ns (<= kScal) at
+// base_s + k -- until all carry tag `seq`.  All loads are issued together;
+// while data is missing only one outstanding word is polled, then the
+// missing ones are reissued.  Returns false on abort or timeout.
+constexpr int kMaxRun = 8;
+__device__ __forceinline__ bool gather3(const uint64_t* base_r, long long str_r,
+                                        int nr, const uint64_t* base_c,
+                                        long long str_c, int nc,
+                                        const uint64_t* base_s, int ns,
+                                        unsigned seq, float* rsum, float* csum,
+                                        float (&sv)[kScal], const Team& tm) {
+  const uint64_t done = (uint64_t)seq << 32;
+  uint64_t vr[kMaxRun], vc[kMaxRun], vs[kScal];
+#pragma unroll
+  for (int k = 0; k < kMaxRun; ++k) {
+    vr[k] = (k < nr) ? get_word(base_r + k * str_r) : done;
+    vc[k] = (k < nc) ? get_word(base_c + k * str_c) : done;
+  }
+#pragma unroll
+  for (int k = 0; k < kScal; ++k) vs[k] = (k < ns) ? get_word(base_s + k) : done;
+  long long t0 = 0;
+  for (;;) {
+    const uint64_t* wait_on = nullptr;
+#pragma unroll
+    for (int k = kScal - 1; k >= 0; --k)
+      if (tag_of(vs[k]) != seq) wait_on = base_s + k;
+#pragma unroll
+    for (int k = kMaxRun - 1; k >= 0; --k) {
+      if (tag_of(vc[k]) != seq) wait_on = base_c + k * str_c;
+      if (tag_of(vr[k]) != seq) wait_on = base_r + k * str_r;
+    }
+    if (!wait_on) break;
+    int spins = 0;
+    while (tag_of(get_word(wait_on)) != seq) {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 31) == 0 && timed_out(tm, t0)) return false;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxRun; ++k) {
+      if (tag_of(vr[k]) != seq) vr[k] = get_word(base_r + k * str_r);
+      if (tag_of(vc[k]) != seq) vc[k] = get_word(base_c + k * str_c);
+    }
+#pragma unroll
+    for (int k = 0; k < kScal; ++k)
+      if (tag_of(vs[k]) != seq) vs[k] = get_word(base_s + k);
+  }
+  float r = 0.f, c = 0.f;
+#pragma unroll
+  for (int k = 0; k < kMaxRun; ++k) {
+    if (k < nr) r += unpack(vr[k]);
+    if (k < nc) c += unpack(vc[k]);
+  }
+  *rsum = r;
+  *csum = c;
+#pragma unroll
+  for (int k = 0; k < kScal; ++k) sv[k] = unpack(vs[k]);
+  return true;
 }
 
 // Scalar exchange: every workgroup posts kScal floats; afterwards sh.scal[w]
 // holds workgroup w's values for this sequence number.
 __device__ bool xchg_scalars(Team& tm, Shared& sh, const float (&mine)[kScal]) {
-  unsigned seq = ++tm.seq;
+  const unsigned seq = ++tm.seq;
   uint64_t* base = tm.xb + (seq & 1u) * tm.par_words +
                    (tm.par_words - (long long)tm.W * kScal);
   __syncthreads();
   if (threadIdx.x < kScal)
     put_word(base + tm.rank * kScal + threadIdx.x,
              pack(seq, mine[threadIdx.x]));
-  bool fail = false;
-  for (int w = threadIdx.x; w < tm.W; w += kThreads) {
-    float v[kScal];
-    if (!gather<kScal>(base + w * kScal, 1, kScal, seq, v, tm)) {
-      fail = true;
-      break;
-    }
+  const int w = threadIdx.x;
+  bool ok = true;
+  if (w < tm.W) {
+    float sv[kScal], r, c;
+    ok = gather3(base, 0, 0, base, 0, 0, base + w * kScal, kScal, seq, &r, &c,
+                 sv, tm);
 #pragma unroll
-    for (int k = 0; k < kScal; ++k) sh.scal[w][k] = v[k];
+    for (int k = 0; k < kScal; ++k) sh.scal[w][k] = sv[k];
   }
-  return !wg_any(sh, fail);
+  return __syncthreads_or(!ok) == 0;
 }
 
 // Team barrier for bulk data written with ordinary stores: release fence,
 // scalar exchange, acquire fence.
 __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  float z[kScal] = {0.f, 0.f, 0.f, 0.f};
-  bool ok = xchg_scalars(tm, sh, z);
+  const float z[kScal] = {0.f, 0.f, 0.f, 0.f};
+  const bool ok = xchg_scalars(tm, sh, z);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok;
 }
@@ -187,17 +225,18 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
         const int idx = tid + kThreads * e;
         const int kk = idx >> 6, mm = idx & 63;
         const int kg = k0 + kk;
-        sh.lp[kk][mm] = (kg < Kd && m0 + mm < M) ? P[(long long)kg * ldp + m0 + mm] : 0.f;
-        sh.lq[kk][mm] = (kg < Kd && n0 + mm < Nc) ? Q[(long long)kg * ldq + n0 + mm] : 0.f;
+        sh.u.g.lp[kk][mm] = (kg < Kd && m0 + mm < M) ? P[(long long)kg * ldp + m0 + mm] : 0.f;
+        sh.u.g.lq[kk][mm] = (kg < Kd && n0 + mm < Nc) ? Q[(long long)kg * ldq + n0 + mm] : 0.f;
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < 32; kk += 2) {
-        const float a = sh.lp[kk + (lane >> 5)][wr * 32 + (lane & 31)];
-        const float b = sh.lq[kk + (lane >> 5)][wc * 32 + (lane & 31)];
+        const float a = sh.u.g.lp[kk + (lane >> 5)][wr * 32 + (lane & 31)];
+        const float b = sh.u.g.lq[kk + (lane >> 5)][wc * 32 + (lane & 31)];
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
       }
     }
+    __syncthreads();
     // 32x32 accumulator layout: lane holds column (lane & 31) and rows
     // 8*(v/4) + 4*(lane/32) + (v%4).
     const int cc = n0 + wc * 32 + (lane & 31);
@@ -210,8 +249,6 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
 }
 
 // ------------------------------------------------------- projection tiles
-// Thread (pr, pc) of the 16 x 16 thread grid holds rows pr + 16a (a < kRA)
-// and columns pc + 16b (b < kCB) of its workgroup's tile.
 struct TileGeom {
   int N, h, w, r0, c0, hv, wv;  // hv, wv: rows / cols of the tile inside N
 };
@@ -228,188 +265,127 @@ __device__ __forceinline__ TileGeom tile_geom(const Team& tm, int N) {
   return g;
 }
 
-// Reduces per-thread row partials rs[kRA] over the 16 lanes that share a row
-// phase (xor 8, 4, 2, 1), halving the live values at each step.  Afterwards
-// lanes pc and pc^1 hold the full tile-row partial of row index a = pc >> 1.
-__device__ __forceinline__ float reduce_rows16(float (&rs)[kRA], int pc) {
-  const bool h3 = pc & 8, h2 = pc & 4, h1 = pc & 2;
-  float t[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = h3 ? rs[k] : rs[k + 4];
-    const float keep = h3 ? rs[k + 4] : rs[k];
-    t[k] = keep + __shfl_xor(send, 8);
-  }
-  float u[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float send = h2 ? t[k] : t[k + 2];
-    const float keep = h2 ? t[k + 2] : t[k];
-    u[k] = keep + __shfl_xor(send, 4);
-  }
-  const float send = h1 ? u[0] : u[1];
-  const float keep = h1 ? u[1] : u[0];
-  float v = keep + __shfl_xor(send, 2);
-  v += __shfl_xor(v, 1);
-  return v;
+// Wave-wide reductions with DPP moves (register-to-register): butterflies
+// within each 16-lane row, then row broadcasts; lane 63 ends up with the
+// result, which is returned to every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_mov(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
 }
-
-// Reduces per-thread column partials cs[kCB] over the 4 row phases of a wave
-// (lanes xor 32, 16).  Afterwards the lane holds 4 partials for columns
-// b = k + 4*bit4(lane) + 8*bit5(lane), k < 4.
-__device__ __forceinline__ void reduce_cols4(float (&cs)[kCB], int lane,
-                                             float (&out)[4]) {
-  const bool h5 = lane & 32, h4 = lane & 16;
-  float t[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float send = h5 ? cs[k] : cs[k + 8];
-    const float keep = h5 ? cs[k + 8] : cs[k];
-    t[k] = keep + __shfl_xor(send, 32);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const float send = h4 ? t[k] : t[k + 4];
-    const float keep = h4 ? t[k + 4] : t[k];
-    out[k] = keep + __shfl_xor(send, 16);
-  }
-}
+#define FPFP_ROW_STEPS(STEP) \
+  STEP(0xb1, 0xf) /* quad_perm [1,0,3,2] */ \
+  STEP(0x4e, 0xf) /* quad_perm [2,3,0,1] */ \
+  STEP(0x141, 0xf) /* row_half_mirror */ \
+  STEP(0x140, 0xf) /* row_mirror */
+#define FPFP_WAVE_STEPS(STEP) \
+  FPFP_ROW_STEPS(STEP) \
+  STEP(0x142, 0xa) /* row_bcast:15 */ \
+  STEP(0x143, 0xc) /* row_bcast:31 */
 
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  const int ninf = __float_as_int(-INFINITY);
+#define STEP(C, R) v = fmaxf(v, __int_as_float(dpp_mov<C, R>(ninf, __float_as_int(v))));
+  FPFP_WAVE_STEPS(STEP)
+#undef STEP
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+#define STEP(C, R)                                                       \
+  {                                                                      \
+    const long long bits = __double_as_longlong(v);                      \
+    const int lo = dpp_mov<C, R>(0, (int)(bits & 0xffffffff));           \
+    const int hi = dpp_mov<C, R>(0, (int)(bits >> 32));                  \
+    v += __longlong_as_double(((long long)hi << 32) | (unsigned)lo);     \
+  }
+  FPFP_WAVE_STEPS(STEP)
+#undef STEP
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 16 lanes of a DPP row; every lane of the row gets it.
+__device__ __forceinline__ float row16_sum(float v) {
+#define STEP(C, R) v += __int_as_float(dpp_mov<C, R>(0, __float_as_int(v)));
+  FPFP_ROW_STEPS(STEP)
+#undef STEP
   return v;
 }
 
-// Polls three strided runs of exchange words -- up to kMaxRun words at
-// base_r + k*str_r, up to kMaxRun at base_c + k*str_c and up to kScal at
-// base_s + k -- until all carry tag `seq`, keeping every load in flight at
-// once.  Returns false on abort or timeout.
-constexpr int kMaxRun = 8;
-__device__ __forceinline__ bool gather3(const uint64_t* base_r, long long str_r,
-                                        int nr, const uint64_t* base_c,
-                                        long long str_c, int nc,
-                                        const uint64_t* base_s, int ns,
-                                        unsigned seq, float* rsum, float* csum,
-                                        float (&sv)[kScal], const Team& tm) {
-  uint64_t vr[kMaxRun], vc[kMaxRun], vs[kScal];
-#pragma unroll
-  for (int k = 0; k < kMaxRun; ++k) {
-    vr[k] = (k < nr) ? get_word(base_r + k * str_r) : ((uint64_t)seq << 32);
-    vc[k] = (k < nc) ? get_word(base_c + k * str_c) : ((uint64_t)seq << 32);
-  }
-#pragma unroll
-  for (int k = 0; k < kScal; ++k)
-    vs[k] = (k < ns) ? get_word(base_s + k) : ((uint64_t)seq << 32);
-  int spins = 0;
-  long long t0 = 0;
-  for (;;) {
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < kMaxRun; ++k)
-      ok &= (tag_of(vr[k]) == seq) & (tag_of(vc[k]) == seq);
-#pragma unroll
-    for (int k = 0; k < kScal; ++k) ok &= (tag_of(vs[k]) == seq);
-    if (ok) break;
-    if ((++spins & 63) == 0) {
-      if (__hip_atomic_load(tm.abort_flag, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT) != 0u)
-        return false;
-      const long long now = (long long)wall_clock64();
-      if (t0 == 0) t0 = now;
-      if (now - t0 > tm.timeout) {
-        __hip_atomic_store(tm.abort_flag, 1u, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (int k = 0; k < kMaxRun; ++k) {
-      if (tag_of(vr[k]) != seq) vr[k] = get_word(base_r + k * str_r);
-      if (tag_of(vc[k]) != seq) vc[k] = get_word(base_c + k * str_c);
-    }
-#pragma unroll
-    for (int k = 0; k < kScal; ++k)
-      if (tag_of(vs[k]) != seq) vs[k] = get_word(base_s + k);
-  }
-  float r = 0.f, c = 0.f;
-#pragma unroll
-  for (int k = 0; k < kMaxRun; ++k) {
-    if (k < nr) r += unpack(vr[k]);
-    if (k < nc) c += unpack(vc[k]);
-  }
-  *rsum = r;
-  *csum = c;
-#pragma unroll
-  for (int k = 0; k < kScal; ++k) sv[k] = unpack(vs[k]);
-  return true;
-}
+// Cycles to sleep (in units of 64 clocks) between posting an exchange and
+// the first load of it: about one store-to-visibility latency, so the first
+// loads usually find the data instead of polling.
+constexpr int kPostSleep = 8;
 
-// Sums of the register tile (row partials, column partials, tile total,
-// max|dY| in dm) posted to the team; then reads back the full row sums of
-// this tile's rows, full column sums of its columns, s = 1^T Y 1 and the
-// team's max|dY|, and forms a (rows) and b (cols) in sh.a_l / sh.b_l.
-// Returns false on abort; *s_out = s, *dmax_out = max|dY|.
+// One team exchange of a pass.  In: each thread's row partials rs[a] (over
+// its kCB columns), column partials cs[b] (over its kRA rows) and its
+// max|dY| dm.  Reduces them over the workgroup (rows with DPP within the 16
+// lanes that share them, columns through LDS), posts the tile's row /
+// column partials, total (float64 as hi + lo floats) and max|dY|, and
+// gathers the full row sums of the tile's rows, column sums of its columns,
+// s = 1^T Y 1 and the team's max|dY|.  Leaves a (rows) and b (columns) of P1
+// in sh.a_l / sh.b_l.  Returns false on abort.
 __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
-                              float (&rs)[kRA], float (&cs)[kCB], float dm,
-                              double* s_out, float* dmax_out) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pc = lane & 15, pr = wave * 4 + (lane >> 4);
-  // --- in-workgroup reductions
-  const float rsum = reduce_rows16(rs, pc);
-  float c4[4];
-  reduce_cols4(cs, lane, c4);
-  const float dw = wave_max(dm);
-  __syncthreads();
-  if ((pc & 1) == 0) sh.rowred[pr + 16 * (pc >> 1)] = rsum;
+                              const float (&rs)[kRA], const float (&cs)[kCB],
+                              float dm, double* s_out, float* dmax_out) {
+  const int tid = threadIdx.x, pr = tid >> 4, pc = tid & 15;
+  const int lane = tid & 63, wave = tid >> 6;
   {
-    const int bb = 4 * ((lane >> 4) & 1) + 8 * ((lane >> 5) & 1);
+    // row partials: lane pc of the row group keeps the sum for a = pc
+    float mine = 0.f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sh.colred[wave][pc + 16 * (bb + k)] = c4[k];
+    for (int a = 0; a < kRA; ++a) {
+      const float v = row16_sum(rs[a]);
+      mine = (pc == a) ? v : mine;
+    }
+    sh.lrow[pr + 16 * pc] = mine;
   }
-  if (lane == 0) sh.wred[wave] = dw;
+#pragma unroll
+  for (int b = 0; b < kCB; ++b) sh.u.lcol[pr][pc + 16 * b] = cs[b];
+  {
+    const float wm = wave_max(dm);
+    if (lane == 0) sh.wred[wave] = wm;
+  }
   __syncthreads();
-  const float rowpart = (tid < kTileRows) ? sh.rowred[tid] : 0.f;
-  const float colpart = sh.colred[0][tid] + sh.colred[1][tid] +
-                        sh.colred[2][tid] + sh.colred[3][tid];
+  // thread t: tile row t and tile column t
+  const int t = tid;
+  const float rpart = sh.lrow[t];
+  float cpart = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) cpart += sh.u.lcol[k][t];
   const float dmw = fmaxf(fmaxf(sh.wred[0], sh.wred[1]),
                           fmaxf(sh.wred[2], sh.wred[3]));
-  // tile total in float64 (fixed order)
-  double ttot = 0.0;
-  if (wave == 0) {
-    ttot = (double)sh.rowred[lane] + (double)sh.rowred[lane + 64];
-    ttot = wave_sum_d(ttot);
+  // tile total in float64 over the row partials (one partial per wave)
+  {
+    const double wt = wave_sum_d((double)rpart);
+    if (lane == 0) sh.dtile[wave] = wt;
   }
+
+  const double Nd = (double)g.N, invN = 1.0 / Nd;
   double s;
   float dmax, rfull, cfull;
   if (tm.W == 1) {
     // single-workgroup team: the tile is the whole matrix
-    rfull = rowpart;
-    cfull = colpart;
-    if (tid == 0) {
-      sh.dred[1] = ttot;
-      sh.wred[0] = dmw;
-    }
     __syncthreads();
-    s = sh.dred[1];
-    dmax = sh.wred[0];
+    rfull = rpart;
+    cfull = cpart;
+    s = ((sh.dtile[0] + sh.dtile[1]) + sh.dtile[2]) + sh.dtile[3];
+    dmax = dmw;
   } else {
-    // --- post
     const unsigned seq = ++tm.seq;
     uint64_t* buf = tm.xb + (seq & 1u) * tm.par_words;
     const long long NPR = (long long)tm.TR * g.h, NPC = (long long)tm.TC * g.w;
     uint64_t* rowp = buf;                        // [TC][NPR]
     uint64_t* colp = buf + tm.TC * NPR;          // [TR][NPC]
     uint64_t* scal = buf + (tm.par_words - (long long)tm.W * kScal);
-    if (tid < g.h) put_word(rowp + tm.tc * NPR + g.r0 + tid, pack(seq, rowpart));
-    if (tid < g.w) put_word(colp + tm.tr * NPC + g.c0 + tid, pack(seq, colpart));
+    if (t < g.h) put_word(rowp + tm.tc * NPR + g.r0 + t, pack(seq, rpart));
+    if (t < g.w) put_word(colp + tm.tr * NPC + g.c0 + t, pack(seq, cpart));
+    __syncthreads();
     if (tid == 0) {
+      const double ttot = ((sh.dtile[0] + sh.dtile[1]) + sh.dtile[2]) +
+                          sh.dtile[3];
       const float hi = (float)ttot;
       const float lo = (float)(ttot - (double)hi);
       put_word(scal + tm.rank * kScal + 0, pack(seq, hi));
@@ -417,71 +393,65 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
       put_word(scal + tm.rank * kScal + 2, pack(seq, dmw));
       put_word(scal + tm.rank * kScal + 3, pack(seq, 0.f));
     }
-    // --- gather: this thread's row (TC words), column (TR words) and one
-    // workgroup's scalars, up to 8 + 8 + 4 words in flight together
-    float sv[kScal];
+    __builtin_amdgcn_s_sleep(kPostSleep);
+    // this thread's runs: TC row partials of row t and TR column partials of
+    // column t (in chunks of 8), plus workgroup t's scalars
+    const int nr = t < g.h ? tm.TC : 0, nc = t < g.w ? tm.TR : 0;
     bool ok = true;
     rfull = 0.f;
     cfull = 0.f;
-    for (int k0 = 0; k0 < kMaxTeamSide && ok; k0 += kMaxRun) {
-      if (k0 >= tm.TC && k0 >= tm.TR) break;
-      const int nr = tid < g.h ? min(kMaxRun, tm.TC - k0) : 0;
-      const int nc = tid < g.w ? min(kMaxRun, tm.TR - k0) : 0;
-      float r, c;
-      ok = gather3(rowp + k0 * NPR + g.r0 + tid, NPR, nr,
-                   colp + k0 * NPC + g.c0 + tid, NPC, nc, scal + tid * kScal,
-                   (k0 == 0 && tid < tm.W) ? kScal : 0, seq, &r, &c, sv, tm);
+    for (int k0 = 0; k0 < max(max(nr, nc), 1) && ok; k0 += kMaxRun) {
+      float r, c, sv[kScal];
+      const bool first = k0 == 0;
+      ok = gather3(rowp + k0 * NPR + g.r0 + t, NPR, min(kMaxRun, nr - k0),
+                   colp + k0 * NPC + g.c0 + t, NPC, min(kMaxRun, nc - k0),
+                   scal + tid * kScal, (first && tid < tm.W) ? kScal : 0, seq,
+                   &r, &c, sv, tm);
       rfull += r;
       cfull += c;
-      if (k0 == 0 && tid < tm.W) {
+      if (first && tid < tm.W) {
 #pragma unroll
         for (int k = 0; k < kScal; ++k) sh.scal[tid][k] = sv[k];
       }
     }
     if (__syncthreads_or(!ok)) return false;
-    // --- team scalars: s in float64 (fixed order), max|dY|
+    // team scalars: s in float64 (fixed order), max|dY|
     if (wave == 0) {
-      double t = 0.0;
+      double tsum = 0.0;
       float m = 0.f;
       for (int w = lane; w < tm.W; w += 64) {
-        t += (double)sh.scal[w][0] + (double)sh.scal[w][1];
+        tsum += (double)sh.scal[w][0] + (double)sh.scal[w][1];
         m = fmaxf(m, sh.scal[w][2]);
       }
-      t = wave_sum_d(t);
+      tsum = wave_sum_d(tsum);
       m = wave_max(m);
       if (lane == 0) {
-        sh.dred[1] = t;
+        sh.dred[0] = tsum;
         sh.wred[0] = m;
       }
     }
     __syncthreads();
-    s = sh.dred[1];
+    s = sh.dred[0];
     dmax = sh.wred[0];
   }
-  const double Nd = (double)g.N, invN = 1.0 / Nd;
-  const double sterm = (s - Nd) * invN * invN;
-  if (tid < kTileRows)
-    sh.a_l[tid] = (tid < g.hv) ? (float)((1.0 - (double)rfull) * invN + sterm)
-                               : -INFINITY;
-  sh.b_l[tid] = (tid < g.wv) ? (float)((1.0 - (double)cfull) * invN) : -INFINITY;
+  sh.a_l[t] = (t < g.hv) ? (float)((1.0 - (double)rfull) * invN +
+                                   (s - Nd) * invN * invN)
+                         : -INFINITY;
+  sh.b_l[t] = (t < g.wv) ? (float)((1.0 - (double)cfull) * invN) : -INFINITY;
   *s_out = s;
   *dmax_out = dmax;
   __syncthreads();
   return true;
 }
 
-__device__ __forceinline__ void load_ab(const Shared& sh, float (&av)[kRA],
-                                        float (&bv)[kCB], int pr, int pc) {
-#pragma unroll
-  for (int a = 0; a < kRA; ++a) av[a] = sh.a_l[pr + 16 * a];
-#pragma unroll
-  for (int b = 0; b < kCB; ++b) bv[b] = sh.b_l[pc + 16 * b];
-}
+// ------------------------------------------------------ tile I/O and loops
+// Entry (a, b) of this thread's tile share: register Yr[a][b] for
+// a < kRegRows, else LDS sh.ly[(a - kRegRows) * kCB + b][tid].
+#define FPFP_LY(a, b) sh.ly[((a) - kRegRows) * kCB + (b)][threadIdx.x]
 
-// ------------------------------------------------------ register tile I/O
 // Y tile <-> global N x N row-major matrix.  Padding entries read as 0.
-__device__ __forceinline__ void load_tile(float (&Yr)[kRA][kCB],
-                                          const float* Y, int N,
+__device__ __forceinline__ void load_tile(float (&Yr)[kRegRows][kCB],
+                                          Shared& sh, const float* Y, int N,
                                           const TileGeom& g, int pr, int pc) {
   const int hv = opaque(g.hv), wv = opaque(g.wv);
 #pragma unroll
@@ -489,14 +459,18 @@ __device__ __forceinline__ void load_tile(float (&Yr)[kRA][kCB],
     const int li = pr + 16 * a;
     const float* rp = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
 #pragma unroll
-    for (int b = 0; b < kCB; ++b)
-      Yr[a][b] = (li < hv && pc + 16 * b < wv) ? rp[16 * b] : 0.f;
+    for (int b = 0; b < kCB; ++b) {
+      const float v = (li < hv && pc + 16 * b < wv) ? rp[16 * b] : 0.f;
+      if (a < kRegRows) Yr[a][b] = v;
+      else FPFP_LY(a, b) = v;
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-__device__ __forceinline__ void store_tile(const float (&Yr)[kRA][kCB],
-                                           float* Y, int N, const TileGeom& g,
-                                           int pr, int pc) {
+__device__ __forceinline__ void store_tile(const float (&Yr)[kRegRows][kCB],
+                                           Shared& sh, float* Y, int N,
+                                           const TileGeom& g, int pr, int pc) {
   const int hv = opaque(g.hv), wv = opaque(g.wv);
 #pragma unroll
   for (int a = 0; a < kRA; ++a) {
@@ -504,17 +478,19 @@ __device__ __forceinline__ void store_tile(const float (&Yr)[kRA][kCB],
     float* rp = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
 #pragma unroll
     for (int b = 0; b < kCB; ++b)
-      if (li < hv && pc + 16 * b < wv) rp[16 * b] = Yr[a][b];
+      if (li < hv && pc + 16 * b < wv)
+        rp[16 * b] = (a < kRegRows) ? Yr[a][b] : FPFP_LY(a, b);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Steps 4-7 on the register tile.  Returns false on abort; sets *numeric
+// Steps 4-7 on the on-chip tile.  Returns false on abort; sets *numeric
 // when a sum or max|dY| is not finite.
-__device__ __forceinline__ bool inner_loop(float (&Yr)[kRA][kCB], Team& tm,
-                                           Shared& sh, const TileGeom& g,
-                                           int max_inner, float tol,
-                                           DevInfo& info, bool* numeric,
-                                           int pr, int pc) {
+__device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
+                                           Team& tm, Shared& sh,
+                                           const TileGeom& g, int max_inner,
+                                           float tol, DevInfo& info,
+                                           bool* numeric, int pr, int pc) {
   float rs[kRA], cs[kCB];
 #pragma unroll
   for (int a = 0; a < kRA; ++a) rs[a] = 0.f;
@@ -524,8 +500,9 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRA][kCB], Team& tm,
   for (int a = 0; a < kRA; ++a)
 #pragma unroll
     for (int b = 0; b < kCB; ++b) {
-      rs[a] += Yr[a][b];
-      cs[b] += Yr[a][b];
+      const float y = (a < kRegRows) ? Yr[a][b] : FPFP_LY(a, b);
+      rs[a] += y;
+      cs[b] += y;
     }
   double s;
   float d = 0.f;
@@ -535,24 +512,28 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRA][kCB], Team& tm,
   d = 0.f;
   if (!*numeric) {
     for (u = 1; u <= max_inner; ++u) {
-      float av[kRA], bv[kCB];
-      load_ab(sh, av, bv, pr, pc);
-      float dm = 0.f;
+      float bv[kCB];
 #pragma unroll
-      for (int a = 0; a < kRA; ++a) rs[a] = 0.f;
+      for (int b = 0; b < kCB; ++b) bv[b] = sh.b_l[pc + 16 * b];
+      float dm = 0.f;
 #pragma unroll
       for (int b = 0; b < kCB; ++b) cs[b] = 0.f;
 #pragma unroll
-      for (int a = 0; a < kRA; ++a)
+      for (int a = 0; a < kRA; ++a) {
+        const float av = sh.a_l[pr + 16 * a];
+        float r = 0.f;
 #pragma unroll
         for (int b = 0; b < kCB; ++b) {
-          const float y = Yr[a][b];
-          const float dd = fmaxf((y + av[a]) + bv[b], 0.f);
+          const float y = (a < kRegRows) ? Yr[a][b] : FPFP_LY(a, b);
+          const float dd = fmaxf((y + av) + bv[b], 0.f);
           dm = fmaxf(dm, fabsf(dd - y));
-          rs[a] += dd;
+          r += dd;
           cs[b] += dd;
-          Yr[a][b] = dd;
+          if (a < kRegRows) Yr[a][b] = dd;
+          else FPFP_LY(a, b) = dd;
         }
+        rs[a] = r;
+      }
       if (!exchange_sums(tm, sh, g, rs, cs, dm, &s, &d)) return false;
       if (!isfinite(s) || !isfinite(d)) {
         *numeric = true;
@@ -584,13 +565,14 @@ __device__ __forceinline__ float wg_max(Shared& sh, float v) {
 __global__ void __launch_bounds__(kThreads, 1)
 fastpfp_persistent(LaunchDesc L) {
   __shared__ Shared sh;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pc = lane & 15, pr = wave * 4 + (lane >> 4);
+  const int tid = threadIdx.x;
+  const int pr = tid >> 4, pc = tid & 15;
 
-  // XCD-aware team membership: workgroup b runs on XCD b % 8, so walking the
-  // grid XCD by XCD keeps each team of W <= G/8 on one die.
-  const int G = gridDim.x, per = G / kXcds;
-  const int v = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  // Team membership.  Workgroup b runs on XCD b % 8; numbering the grid XCD
+  // by XCD keeps a team of W <= cpx (compute units per XCD) on one die.
+  const int cpx = L.cus_per_xcd, b = blockIdx.x;
+  const int slot = b / (kXcds * cpx);
+  const int v = slot * kXcds * cpx + (b % kXcds) * cpx + (b / kXcds) % cpx;
   Team tm;
   tm.W = L.W;
   tm.team = v / L.W;
@@ -614,7 +596,7 @@ fastpfp_persistent(LaunchDesc L) {
       sh.wred[0] = __uint_as_float(atomicAdd(L.queue, 1u));
     __syncthreads();
     {
-      float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
+      const float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
       if (!xchg_scalars(tm, sh, post)) return;
     }
     const unsigned pidx =
@@ -625,38 +607,48 @@ fastpfp_persistent(LaunchDesc L) {
     float* const Y = pd.Y ? pd.Y : Yws;
     const TileGeom g = tile_geom(tm, N);
     DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f};
-    float Yr[kRA][kCB];
+    float Yr[kRegRows][kCB];
 
     if (pd.mode == kModeProject) {
-      load_tile(Yr, Y, N, g, pr, pc);
+      load_tile(Yr, sh, Y, N, g, pr, pc);
       bool numeric = false;
       if (!inner_loop(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info, &numeric,
                       pr, pc))
         return;
-      store_tile(Yr, Y, N, g, pr, pc);
+      store_tile(Yr, sh, Y, N, g, pr, pc);
       info.status = numeric ? 5 : 0;
     } else {
       float* const X = pd.X;
       const int ldx = pd.ldx;
+      // Entries of the tile inside the n x n' block: tile-local rows
+      // li < rmax, columns lj < cmax.
+      const int rmax_ = min(g.hv, n - g.r0), cmax_ = min(g.wv, np - g.c0);
       // ---- initialisation (Algorithm 1, step 1): X0 and the slack
       {
         const int hv = opaque(g.hv), wv = opaque(g.wv);
+        const int rmax = opaque(rmax_), cmax = opaque(cmax_);
         const float c0 = pd.init_c;
         const bool init_x = !pd.init_user, zero_y = !pd.y_user;
 #pragma unroll
-        for (int a = 0; a < kRA; ++a)
+        for (int a = 0; a < kRA; ++a) {
+          const int li = pr + 16 * a;
+          if (li < hv) {
+            float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+            float* yrow = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
 #pragma unroll
-          for (int b = 0; b < kCB; ++b) {
-            const int li = pr + 16 * a, lj = pc + 16 * b;
-            const int i = g.r0 + li, j = g.c0 + lj;
-            if (li < hv && lj < wv) {
-              if (i < n && j < np) {
-                if (init_x) X[(long long)i * ldx + j] = c0;
-              } else if (zero_y) {
-                Y[(long long)i * N + j] = 0.f;
+            for (int bb = 0; bb < kCB; ++bb) {
+              const int lj = pc + 16 * bb;
+              if (lj < wv) {
+                if (li < rmax && lj < cmax) {
+                  if (init_x) xrow[16 * bb] = c0;
+                } else if (zero_y) {
+                  yrow[16 * bb] = 0.f;
+                }
               }
             }
           }
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
       if (!team_sync_bulk(tm, sh)) return;
       for (int t = 1; t <= pd.max_outer; ++t) {
@@ -684,7 +676,7 @@ fastpfp_persistent(LaunchDesc L) {
         }
         if (!team_sync_bulk(tm, sh)) return;
         // ---- steps 4-7
-        load_tile(Yr, Y, N, g, pr, pc);
+        load_tile(Yr, sh, Y, N, g, pr, pc);
         bool numeric = false;
         if (!inner_loop(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
                         &numeric, pr, pc))
@@ -693,30 +685,34 @@ fastpfp_persistent(LaunchDesc L) {
           info.status = 5;
           break;
         }
-        store_tile(Yr, Y, N, g, pr, pc);
-        // ---- step 8: X_new = (1 - alpha) X + alpha Y[:n,:np]
+        store_tile(Yr, sh, Y, N, g, pr, pc);
+        // ---- step 8: X_new = (1 - alpha) X + alpha Y[:n,:np], kept in the
+        // tile's storage
         const float alpha = pd.alpha, beta = 1.f - pd.alpha;
         float mloc = 0.f;
         {
-          const int hv = opaque(g.hv), wv = opaque(g.wv);
-          const int nx = opaque(n), npx = opaque(np);
+          const int rmax = opaque(rmax_), cmax = opaque(cmax_);
 #pragma unroll
-          for (int a = 0; a < kRA; ++a)
+          for (int a = 0; a < kRA; ++a) {
+            const int li = pr + 16 * a;
+            if (li < rmax) {
+              const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
 #pragma unroll
-            for (int b = 0; b < kCB; ++b) {
-              const int li = pr + 16 * a, lj = pc + 16 * b;
-              const int i = g.r0 + li, j = g.c0 + lj;
-              if (li < hv && lj < wv && i < nx && j < npx) {
-                const float xo = X[(long long)i * ldx + j];
-                const float xn = beta * xo + alpha * Yr[a][b];
-                Yr[a][b] = xn;
-                mloc = fmaxf(mloc, xn);
-              }
+              for (int bb = 0; bb < kCB; ++bb)
+                if (pc + 16 * bb < cmax) {
+                  const float y = (a < kRegRows) ? Yr[a][bb] : FPFP_LY(a, bb);
+                  const float xn = beta * xrow[16 * bb] + alpha * y;
+                  if (a < kRegRows) Yr[a][bb] = xn;
+                  else FPFP_LY(a, bb) = xn;
+                  mloc = fmaxf(mloc, xn);
+                }
             }
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
         // ---- step 9: m = max X_new over the team, X = X_new / m
         {
-          float post[kScal] = {wg_max(sh, mloc), 0.f, 0.f, 0.f};
+          const float post[kScal] = {wg_max(sh, mloc), 0.f, 0.f, 0.f};
           if (!xchg_scalars(tm, sh, post)) return;
         }
         float m = 0.f;
@@ -728,25 +724,27 @@ fastpfp_persistent(LaunchDesc L) {
         const bool norm = pd.normalize;
         float eloc = 0.f;
         {
-          const int hv = opaque(g.hv), wv = opaque(g.wv);
-          const int nx = opaque(n), npx = opaque(np);
+          const int rmax = opaque(rmax_), cmax = opaque(cmax_);
 #pragma unroll
-          for (int a = 0; a < kRA; ++a)
+          for (int a = 0; a < kRA; ++a) {
+            const int li = pr + 16 * a;
+            if (li < rmax) {
+              float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
 #pragma unroll
-            for (int b = 0; b < kCB; ++b) {
-              const int li = pr + 16 * a, lj = pc + 16 * b;
-              const int i = g.r0 + li, j = g.c0 + lj;
-              if (li < hv && lj < wv && i < nx && j < npx) {
-                float* xp = X + (long long)i * ldx + j;
-                const float xo = *xp;
-                const float xv = norm ? Yr[a][b] / m : Yr[a][b];
-                eloc = fmaxf(eloc, fabsf(xv - xo));
-                *xp = xv;
-              }
+              for (int bb = 0; bb < kCB; ++bb)
+                if (pc + 16 * bb < cmax) {
+                  const float xn = (a < kRegRows) ? Yr[a][bb] : FPFP_LY(a, bb);
+                  const float xv = norm ? xn / m : xn;
+                  eloc = fmaxf(eloc, fabsf(xv - xrow[16 * bb]));
+                  xrow[16 * bb] = xv;
+                }
             }
+            // one row of divisions at a time keeps register use bounded
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
         {
-          float post[kScal] = {wg_max(sh, eloc), 0.f, 0.f, 0.f};
+          const float post[kScal] = {wg_max(sh, eloc), 0.f, 0.f, 0.f};
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           if (!xchg_scalars(tm, sh, post)) return;
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
