@@ -65,17 +65,20 @@ struct Team {
   long long timeout;   // wall clock ticks one wait may last
 };
 
+constexpr int kGT = 128;  // GEMM output tile (kGT x kGT per workgroup)
+constexpr int kGK = 16;   // GEMM k-rows staged per step
+
 struct Shared {
-  // LDS-resident part of the tile: entry (a, b) of thread t at
-  // ly[(a - kRegRows) * kCB + b][t] (consecutive threads, consecutive banks)
-  float ly[kLdsRows * kCB][kThreads];
   union {
-    struct {  // GEMM operand staging
-      float lp[32][64];
-      float lq[32][64];
+    // LDS-resident part of the projection tile: entry (a, b) of thread t at
+    // ly[(a - kRegRows) * kCB + b][t] (consecutive threads, consecutive banks)
+    float ly[kLdsRows * kCB][kThreads];
+    struct {  // GEMM operand staging (the tile lives in global Y meanwhile)
+      float lp[kGK][kGT];
+      float lq[kGK][kGT];
     } g;
-    float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
-  } u;
+  } t;
+  float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
   float lrow[kTileRows];
   float a_l[kTileRows];
   float b_l[kTileCols];
@@ -201,50 +204,81 @@ __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
 
 // ------------------------------------------------------------------- GEMM
 // C[m][c] = sum_k P[k*ldp + m] * Q[k*ldq + c] for m < M, c < Nc, k < Kd,
-// in 64 x 64 output tiles dealt round-robin over the team.  Each wave owns a
-// 32 x 32 block computed with v_mfma_f32_32x32x2_f32; operands are staged
-// through LDS 32 k-rows at a time.  epi(m, c, value) stores one result.
+// in kGT x kGT output tiles dealt round-robin over the team.  Each wave owns
+// a 64 x 64 quarter as 2 x 2 blocks of v_mfma_f32_32x32x2_f32; operands are
+// staged through LDS kGK k-rows at a time, the next step's operands being
+// loaded into registers while the current one computes.  epi(m, c, value)
+// stores one result.
 template <class Epi>
 __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
                               const float* __restrict__ Q, int ldq, int M,
                               int Nc, int Kd, const Team& tm, Shared& sh,
                               Epi epi) {
+  constexpr int kPer = kGK * kGT / kThreads;  // operand elements per thread
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int tiles_m = (M + 63) / 64, tiles_n = (Nc + 63) / 64;
+  const int tiles_m = (M + kGT - 1) / kGT, tiles_n = (Nc + kGT - 1) / kGT;
   const int ntiles = tiles_m * tiles_n;
   for (int q = tm.rank; q < ntiles; q += tm.W) {
-    const int m0 = (q / tiles_n) * 64, n0 = (q % tiles_n) * 64;
-    floatx16 acc;
+    const int m0 = (q / tiles_n) * kGT, n0 = (q % tiles_n) * kGT;
+    floatx16 acc[2][2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-    for (int k0 = 0; k0 < Kd; k0 += 32) {
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+    // element e of this thread's share: k-row (tid + 256 e) / kGT, col % kGT
+    const int mm = tid & (kGT - 1), kb = tid / kGT;
+    const bool pm = m0 + mm < M, qm = n0 + mm < Nc;
+    float pa[kPer], qa[kPer];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) {
+        const int kg = k0 + kb + e * (kThreads / kGT);
+        const bool kin = kg < Kd;
+        pa[e] = (kin && pm) ? P[(long long)kg * ldp + m0 + mm] : 0.f;
+        qa[e] = (kin && qm) ? Q[(long long)kg * ldq + n0 + mm] : 0.f;
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < Kd; k0 += kGK) {
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int idx = tid + kThreads * e;
-        const int kk = idx >> 6, mm = idx & 63;
-        const int kg = k0 + kk;
-        sh.u.g.lp[kk][mm] = (kg < Kd && m0 + mm < M) ? P[(long long)kg * ldp + m0 + mm] : 0.f;
-        sh.u.g.lq[kk][mm] = (kg < Kd && n0 + mm < Nc) ? Q[(long long)kg * ldq + n0 + mm] : 0.f;
+      for (int e = 0; e < kPer; ++e) {
+        sh.t.g.lp[kb + e * (kThreads / kGT)][mm] = pa[e];
+        sh.t.g.lq[kb + e * (kThreads / kGT)][mm] = qa[e];
       }
       __syncthreads();
+      if (k0 + kGK < Kd) fetch(k0 + kGK);
 #pragma unroll
-      for (int kk = 0; kk < 32; kk += 2) {
-        const float a = sh.u.g.lp[kk + (lane >> 5)][wr * 32 + (lane & 31)];
-        const float b = sh.u.g.lq[kk + (lane >> 5)][wc * 32 + (lane & 31)];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      for (int kk = 0; kk < kGK; kk += 2) {
+        const int kr = kk + (lane >> 5), col = lane & 31;
+        const float a0 = sh.t.g.lp[kr][wr * 64 + col];
+        const float a1 = sh.t.g.lp[kr][wr * 64 + 32 + col];
+        const float b0 = sh.t.g.lq[kr][wc * 64 + col];
+        const float b1 = sh.t.g.lq[kr][wc * 64 + 32 + col];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
       }
     }
     __syncthreads();
     // 32x32 accumulator layout: lane holds column (lane & 31) and rows
     // 8*(v/4) + 4*(lane/32) + (v%4).
-    const int cc = n0 + wc * 32 + (lane & 31);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int mm = m0 + wr * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      if (mm < M && cc < Nc) epi(mm, cc, acc[v]);
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int cc = n0 + wc * 64 + 32 * j + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int mr = m0 + wr * 64 + 32 * i + 8 * (v >> 2) +
+                         4 * (lane >> 5) + (v & 3);
+          if (mr < M && cc < Nc) epi(mr, cc, acc[i][j][v]);
+        }
+      }
   }
 }
 
@@ -343,7 +377,7 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
     sh.lrow[pr + 16 * pc] = mine;
   }
 #pragma unroll
-  for (int b = 0; b < kCB; ++b) sh.u.lcol[pr][pc + 16 * b] = cs[b];
+  for (int b = 0; b < kCB; ++b) sh.lcol[pr][pc + 16 * b] = cs[b];
   {
     const float wm = wave_max(dm);
     if (lane == 0) sh.wred[wave] = wm;
@@ -354,7 +388,7 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
   const float rpart = sh.lrow[t];
   float cpart = 0.f;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) cpart += sh.u.lcol[k][t];
+  for (int k = 0; k < 16; ++k) cpart += sh.lcol[k][t];
   const float dmw = fmaxf(fmaxf(sh.wred[0], sh.wred[1]),
                           fmaxf(sh.wred[2], sh.wred[3]));
   // tile total in float64 over the row partials (one partial per wave)
@@ -447,7 +481,7 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
 // ------------------------------------------------------ tile I/O and loops
 // Entry (a, b) of this thread's tile share: register Yr[a][b] for
 // a < kRegRows, else LDS sh.ly[(a - kRegRows) * kCB + b][tid].
-#define FPFP_LY(a, b) sh.ly[((a) - kRegRows) * kCB + (b)][threadIdx.x]
+#define FPFP_LY(a, b) sh.t.ly[((a) - kRegRows) * kCB + (b)][threadIdx.x]
 
 // Y tile <-> global N x N row-major matrix.  Padding entries read as 0.
 __device__ __forceinline__ void load_tile(float (&Yr)[kRegRows][kCB],
