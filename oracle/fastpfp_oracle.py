@@ -57,10 +57,29 @@ DEFAULT_I1 = 1000
 
 
 # ------------------------------------------------------------------ basics
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (8-bit significand), to nearest, ties to even,
+    through float32; returned as float64.  Defines the reduced-precision
+    product recipe below, not part of the paper."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(
+        np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def gradient(A: np.ndarray, X: np.ndarray, B: np.ndarray,
-             K: Optional[np.ndarray], lam: float) -> np.ndarray:
-    """Sec. 4.1: grad f(X) = A X A' + lambda K (A, A' symmetric)."""
-    G = (A @ X) @ B
+             K: Optional[np.ndarray], lam: float,
+             products: str = "fp64") -> np.ndarray:
+    """Sec. 4.1: grad f(X) = A X A' + lambda K (A, A' symmetric).
+
+    products="bf16" evaluates A X A' with bfloat16 operands: A, A' and X
+    rounded to bfloat16, T = A X formed exactly and rounded to bfloat16,
+    then T A' formed exactly (the reduced-precision form of the products)."""
+    if products == "bf16":
+        T = bf16_round(bf16_round(A) @ bf16_round(X))
+        G = T @ bf16_round(B)
+    else:
+        G = (A @ X) @ B
     if lam != 0.0:
         G = G + lam * K
     return G
@@ -156,7 +175,7 @@ def fastpfp(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
             max_inner: int = DEFAULT_I1, X0: Optional[np.ndarray] = None,
             Y0: Optional[np.ndarray] = None, normalize_max: bool = True,
             projector: Optional[Callable[[np.ndarray], np.ndarray]] = None,
-            ) -> SolveResult:
+            products: str = "fp64") -> SolveResult:
     """Algorithm 1 in float64.
 
     ``projector`` replaces the inner repeat (tests of Lemma 1 / Theorem 1
@@ -173,7 +192,7 @@ def fastpfp(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
     t = 0
     for t in range(1, max_outer + 1):
         Y = Y.copy()
-        Y[:n, :np_] = gradient(A, X, B, K, lam)          # step 3
+        Y[:n, :np_] = gradient(A, X, B, K, lam, products)  # step 3
         if projector is None:
             res = inner_projection(Y, eps2, max_inner)   # steps 4-7
             Y = res.Y

@@ -103,8 +103,6 @@ fastpfp_status check_params(fastpfp_t h, const fastpfp_params* p) {
     return fail(h, FASTPFP_ERR_INVALID_ARG, "iteration caps must be >= 1");
   if (p->precision != FASTPFP_FP32 && p->precision != FASTPFP_BF16)
     return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown precision %d", p->precision);
-  if (p->precision == FASTPFP_BF16)
-    return fail(h, FASTPFP_ERR_UNSUPPORTED, "BF16 products are not built yet");
   if (p->init != FASTPFP_INIT_UNIFORM && p->init != FASTPFP_INIT_USER)
     return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown init %d", p->init);
   if (!(p->init_scale >= 0.0) || !std::isfinite(p->init_scale))
@@ -116,12 +114,13 @@ fastpfp_status check_params(fastpfp_t h, const fastpfp_params* p) {
 
 // Workspace layout of one launch, in bytes from the workspace base.
 struct Layout {
-  size_t pairs, infos, queue, trace, xbuf, wsT, wsY, total;
-  long long xbuf_stride, wsT_stride, wsY_stride;
+  size_t pairs, infos, queue, trace, xbuf, wsT, wsY, wsH, total;
+  long long xbuf_stride, wsT_stride, wsY_stride, wsH_stride;
 };
 
 Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
-                  int max_nnp, int max_outer, bool need_y, bool need_trace) {
+                  int max_nnp, int max_outer, bool need_y, bool need_trace,
+                  bool need_bf16) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   Layout L{};
   size_t o = 0;
@@ -142,6 +141,11 @@ Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
   L.wsY_stride = need_y ? (((long long)maxN * maxN + 63) & ~63LL) : 0;
   L.wsY = o;
   o = up(o + sizeof(float) * L.wsY_stride * num_teams);
+  // BF16 shadows: 4 matrices of Np x Np, Np = maxN rounded up to 128
+  const long long Np = (maxN + 127) / 128 * 128;
+  L.wsH_stride = need_bf16 ? 4 * Np * Np : 0;
+  L.wsH = o;
+  o = up(o + sizeof(uint16_t) * L.wsH_stride * num_teams);
   L.total = o;
   return L;
 }
@@ -196,8 +200,10 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   bool need_y = false;
   for (auto& q : pairs) need_y |= (q.Y == nullptr);
   const int max_outer = mode == fpfp::kModeSolve ? p->max_outer : 1;
+  const bool need_bf16 = mode == fpfp::kModeSolve &&
+                         p->precision == FASTPFP_BF16;
   Layout lay = layout_for((int)pairs.size(), num_teams, pl, maxN, max_nnp,
-                          max_outer, need_y, want_trace);
+                          max_outer, need_y, want_trace, need_bf16);
   fastpfp_status st = ensure_ws(h, lay.total);
   if (st != FASTPFP_OK) return st;
   char* base = (char*)h->ws;
@@ -255,6 +261,8 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   L.wsT_stride = lay.wsT_stride;
   L.wsY = (float*)(base + lay.wsY);
   L.wsY_stride = lay.wsY_stride;
+  L.wsH = (uint16_t*)(base + lay.wsH);
+  L.wsH_stride = lay.wsH_stride;
   L.queue = (unsigned*)(base + lay.queue);
   L.timeout_ticks = 100000000LL * 20;  // 20 s of the 100 MHz wall clock
 

@@ -56,6 +56,8 @@ struct LaunchDesc {
   long long wsT_stride;
   float* wsY;                 // per team: slacked Y (max N x N)
   long long wsY_stride;
+  uint16_t* wsH;              // per team, BF16 products only: A, B, X^T, T
+  long long wsH_stride;       // shadows, each Np x Np (Np = N rounded to 128)
   unsigned* queue;            // [0]: next pair; [1]: abort flag
   long long timeout_ticks;    // wall-clock ticks a wait may last
 };

@@ -67,6 +67,7 @@ struct Team {
 
 constexpr int kGT = 128;  // GEMM output tile (kGT x kGT per workgroup)
 constexpr int kGK = 16;   // GEMM k-rows staged per step
+constexpr int kBK = 32;   // BF16 GEMM k per step
 
 struct Shared {
   union {
@@ -77,6 +78,10 @@ struct Shared {
       float lp[kGK][kGT];
       float lq[kGK][kGT];
     } g;
+    struct {  // BF16 GEMM staging: [row][k], 32 k per step, padded pitch
+      uint16_t lp[kGT][kBK + 8];
+      uint16_t lq[kGT][kBK + 8];
+    } h;
   } t;
   float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
   float lrow[kTileRows];
@@ -277,6 +282,87 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
           const int mr = m0 + wr * 64 + 32 * i + 8 * (v >> 2) +
                          4 * (lane >> 5) + (v & 3);
           if (mr < M && cc < Nc) epi(mr, cc, acc[i][j][v]);
+        }
+      }
+  }
+}
+
+// Round-to-nearest-even float -> bfloat16 bits (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// C[m][c] = sum_k P[m*ld + k] * Q[c*ld + k] with bfloat16 operands and
+// float32 accumulation (v_mfma_f32_32x32x16_bf16), over the zero-padded
+// shadows: Mt, Nt multiples of kGT, Kd a multiple of kBK; every tile is
+// computed and epi(m, c, value) receives all Mt x Nt results.  Each wave
+// owns a 64 x 64 quarter of a kGT x kGT tile; operands are staged through
+// LDS kBK k at a time with the next step prefetched into registers.
+template <class Epi>
+__device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
+                               const uint16_t* __restrict__ Q, int ld, int Mt,
+                               int Nt, int Kd, const Team& tm, Shared& sh,
+                               Epi epi) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tiles_n = Nt / kGT, ntiles = (Mt / kGT) * tiles_n;
+  // this thread stages row tid/2, k-half (tid%2)*16 of both operand tiles
+  const int sr = tid >> 1, sk = (tid & 1) * 16;
+  for (int q = tm.rank; q < ntiles; q += tm.W) {
+    const int m0 = (q / tiles_n) * kGT, n0 = (q % tiles_n) * kGT;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+    const u32x4* prow = (const u32x4*)(P + (long long)(m0 + sr) * ld + sk);
+    const u32x4* qrow = (const u32x4*)(Q + (long long)(n0 + sr) * ld + sk);
+    u32x4 pa0 = prow[0], pa1 = prow[1], qa0 = qrow[0], qa1 = qrow[1];
+    for (int k0 = 0; k0 < Kd; k0 += kBK) {
+      __syncthreads();
+      *(u32x4*)&sh.t.h.lp[sr][sk] = pa0;
+      *(u32x4*)&sh.t.h.lp[sr][sk + 8] = pa1;
+      *(u32x4*)&sh.t.h.lq[sr][sk] = qa0;
+      *(u32x4*)&sh.t.h.lq[sr][sk + 8] = qa1;
+      __syncthreads();
+      if (k0 + kBK < Kd) {
+        const int step = (k0 + kBK) / 8;  // in 16-byte units
+        pa0 = prow[step];
+        pa1 = prow[step + 1];
+        qa0 = qrow[step];
+        qa1 = qrow[step + 1];
+      }
+#pragma unroll
+      for (int ks = 0; ks < kBK; ks += 16) {
+        const int kk = ks + 8 * (lane >> 5), rr = lane & 31;
+        const bf16x8 a0 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + rr][kk];
+        const bf16x8 a1 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + 32 + rr][kk];
+        const bf16x8 b0 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + rr][kk];
+        const bf16x8 b1 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + 32 + rr][kk];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int cc = n0 + wc * 64 + 32 * j + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int mr = m0 + wr * 64 + 32 * i + 8 * (v >> 2) +
+                         4 * (lane >> 5) + (v & 3);
+          epi(mr, cc, acc[i][j][v]);
         }
       }
   }
@@ -623,6 +709,7 @@ fastpfp_persistent(LaunchDesc L) {
   tm.timeout = L.timeout_ticks;
   float* const Tt = L.wsT + (long long)tm.team * L.wsT_stride;
   float* const Yws = L.wsY + (long long)tm.team * L.wsY_stride;
+  uint16_t* const Hws = L.wsH + (long long)tm.team * L.wsH_stride;
 
   for (;;) {
     // ---- next pair: the team leader takes it from the queue and posts it
@@ -684,29 +771,62 @@ fastpfp_persistent(LaunchDesc L) {
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      if (!team_sync_bulk(tm, sh)) return;
-      for (int t = 1; t <= pd.max_outer; ++t) {
-        // ---- step 3: T^T = X^T A  (np x n), then Y[:n,:np] = T B + lam K
-        {
-          float* const Tw = Tt;
-          const int nn = n;
-          team_gemm_f32(X, ldx, pd.A, pd.lda, np, n, n, tm, sh,
-                        [=](int m, int c, float val) {
-                          Tw[(long long)m * nn + c] = val;
-                        });
+      // BF16 products: zero-padded shadows A_h, B_h (converted once per
+      // pair) and X^T_h (the transposed iterate), each Np x Np
+      const bool bf = pd.precision == 1;
+      const int Np = (N + kGT - 1) / kGT * kGT;
+      const long long Np2 = (long long)Np * Np;
+      uint16_t* const Ah = Hws;
+      uint16_t* const Bh = Hws + Np2;
+      uint16_t* const Xh = Hws + 2 * Np2;
+      uint16_t* const Th = Hws + 3 * Np2;
+      if (bf) {
+        const float c0 = pd.init_c;
+        const bool user = pd.init_user;
+        for (long long e = (long long)tm.rank * kThreads + tid; e < Np2;
+             e += (long long)tm.W * kThreads) {
+          const int r = (int)(e / Np), c = (int)(e % Np);
+          Ah[e] = (r < n && c < n) ? f2bf(pd.A[(long long)r * pd.lda + c]) : 0;
+          Bh[e] = (r < np && c < np) ? f2bf(pd.B[(long long)r * pd.ldb + c]) : 0;
+          Xh[e] = (r < np && c < n)
+                      ? f2bf(user ? X[(long long)c * ldx + r] : c0) : 0;
         }
-        if (!team_sync_bulk(tm, sh)) return;
+      }
+      if (!team_sync_bulk(tm, sh)) return;
+      const int Mt = (n + kGT - 1) / kGT * kGT, Nt = (np + kGT - 1) / kGT * kGT;
+      for (int t = 1; t <= pd.max_outer; ++t) {
+        // ---- step 3: Y[:n,:np] = A X B + lam K.  FP32: T^T = X^T A (np x n)
+        // then T B; BF16: T = A X from the shadows, then T B.
         {
           const float lam = pd.lam;
           const float* const Kp = pd.K;
-          const int ldk = pd.ldk, NN = N;
+          const int ldk = pd.ldk, NN = N, nn = n, npp = np;
           float* const Yw = Y;
-          team_gemm_f32(Tt, n, pd.B, pd.ldb, n, np, np, tm, sh,
-                        [=](int m, int c, float val) {
-                          float yv = val;
-                          if (Kp) yv += lam * Kp[(long long)m * ldk + c];
-                          Yw[(long long)m * NN + c] = yv;
-                        });
+          auto out = [=](int m, int c, float val) {
+            if (m < nn && c < npp) {
+              float yv = val;
+              if (Kp) yv += lam * Kp[(long long)m * ldk + c];
+              Yw[(long long)m * NN + c] = yv;
+            }
+          };
+          if (bf) {
+            const int ld = Np;
+            team_gemm_bf16(Ah, Xh, Np, Mt, Nt, (n + kBK - 1) / kBK * kBK, tm,
+                           sh, [=](int m, int c, float val) {
+                             Th[(long long)m * ld + c] = f2bf(val);
+                           });
+            if (!team_sync_bulk(tm, sh)) return;
+            team_gemm_bf16(Th, Bh, Np, Mt, Nt, (np + kBK - 1) / kBK * kBK, tm,
+                           sh, out);
+          } else {
+            float* const Tw = Tt;
+            team_gemm_f32(X, ldx, pd.A, pd.lda, np, n, n, tm, sh,
+                          [=](int m, int c, float val) {
+                            Tw[(long long)m * nn + c] = val;
+                          });
+            if (!team_sync_bulk(tm, sh)) return;
+            team_gemm_f32(Tt, n, pd.B, pd.ldb, n, np, np, tm, sh, out);
+          }
         }
         if (!team_sync_bulk(tm, sh)) return;
         // ---- steps 4-7
@@ -771,6 +891,9 @@ fastpfp_persistent(LaunchDesc L) {
                   const float xv = norm ? xn / m : xn;
                   eloc = fmaxf(eloc, fabsf(xv - xrow[16 * bb]));
                   xrow[16 * bb] = xv;
+                  if (bf)
+                    Xh[(long long)(g.c0 + pc + 16 * bb) * Np + g.r0 + li] =
+                        f2bf(xv);
                 }
             }
             // one row of divisions at a time keeps register use bounded

@@ -232,3 +232,52 @@ def test_batched_equals_single_solves(env):
         np.testing.assert_array_equal(Xb, Xs)
         assert inf["outer_iters"] == info["outer_iters"]
         assert inf["inner_iters_total"] == info["inner_iters_total"]
+
+
+# ------------------------------------------------------ BF16 products
+@pytest.mark.parametrize("n,m", [(70, 90), (90, 70)])
+def test_bf16_products_match_recipe_oracle(env, n, m):
+    """BF16 form against the oracle running the same rounding recipe
+    (A, B, X rounded to bfloat16, T = A X rounded to bfloat16).  The GPU
+    accumulates in float32 and the oracle in float64, so an element of T or
+    of the bfloat16 copy of X can round to the neighbouring bfloat16 value
+    (2^-8 relative in that element) and the difference carries through the
+    later steps; the iterates agree to one bfloat16 ulp of the largest
+    entry, 2^-8 * max|X|."""
+    torch, F, S = env
+    rng = synth.rng_for(98, n * 1000 + m)
+    A = synth.random_weighted_graph(rng, n, 0.3)
+    B = synth.random_weighted_graph(rng, m, 0.3)
+    K = rng.random((n, m))
+    p = synth.GraphPair(A, B, K, 0.5, np.full(n, -1))
+    kw = dict(max_outer=5, max_inner=120)
+    X, info, _ = gpu_solve(env, p, lambda_=0.5, precision=F.BF16, **kw)
+    ref = O.fastpfp(A, B, K, 0.5, products="bf16", **kw)
+    assert np.abs(X - ref.X).max() <= 2.0 ** -8 * np.abs(ref.X).max()
+    assert info["outer_iters"] == ref.outer_iters
+
+
+def test_bf16_and_fp32_config2_full_size(env):
+    """Config 2 (n = 1000, n' = 1200, 200 outliers): error of the FP32 and
+    BF16 forms against the stored FP64 oracle; BF16 keeps the FP32 run's
+    matching accuracy within 0.5 pp and its objective within 1e-3."""
+    torch, F, S = env
+    g = np.load(os.path.join(GOLD, "config2_pair0.npz"))
+    p = synth.config2_pair(0)
+    res = {}
+    for name, prec in (("fp32", F.FP32), ("bf16", F.BF16)):
+        X, info, _ = gpu_solve(env, p, lambda_=p.lam, precision=prec)
+        m = O.hungarian_discretize(X)
+        res[name] = dict(
+            err=float(np.abs(X[g["rows"], g["cols"]] - g["xs"]).max()),
+            acc=O.accuracy(m, p.perm), obj=O.objective(p.A, p.B, p.K, p.lam, m),
+            outer=info["outer_iters"])
+    print(f"config2 oracle: acc {float(g['accuracy']):.4f} "
+          f"obj {float(g['objective']):.6e} outer {int(g['outer'])}")
+    for k, v in res.items():
+        print(f"config2 {k}: max|X - X_fp64| on samples {v['err']:.3e}, "
+              f"acc {v['acc']:.4f}, obj {v['obj']:.6e}, outer {v['outer']}")
+    assert res["fp32"]["err"] <= 1e-4 * float(g["xmax"])
+    assert res["bf16"]["acc"] >= res["fp32"]["acc"] - 0.005
+    assert abs(res["bf16"]["obj"] - res["fp32"]["obj"]) <= \
+        1e-3 * abs(res["fp32"]["obj"])

@@ -414,3 +414,26 @@ def test_damped_update_closed_form_constant_gradient():
                   normalize_max=False)
     np.testing.assert_allclose(r.X, D + (1 - alpha) ** 3 * (X0 - D),
                                atol=1e-13)
+
+
+def test_bf16_rounding_recipe():
+    """Round-to-nearest-even onto an 8-bit significand (7 stored fraction
+    bits): exact on bfloat16 values, halfway cases to even, relative error
+    at most half an ulp, 2^-8."""
+    exact = np.array([1.0, -2.5, 0.0, 3.140625, 2.0 ** -20])
+    np.testing.assert_array_equal(O.bf16_round(exact), exact)
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even (1.0)
+    assert O.bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert O.bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=1000)
+    r = O.bf16_round(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 2.0 ** -16))
+    assert np.abs(r - x).max() > 2.0 ** -10 * np.abs(x).max() / 4
+    # the bf16 product recipe differs from exact products by ~bf16 rounding
+    A, B = rand_sym(rng, 20, 0.5), rand_sym(rng, 20, 0.5)
+    X = rng.random((20, 20))
+    g64 = O.gradient(A, X, B, None, 0.0)
+    g16 = O.gradient(A, X, B, None, 0.0, products="bf16")
+    rel = np.abs(g16 - g64).max() / np.abs(g64).max()
+    assert 1e-5 < rel < 2e-2
