@@ -118,9 +118,9 @@ struct Layout {
   long long xbuf_stride, wsT_stride, wsY_stride, wsH_stride;
 };
 
-Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
+Layout layout_for(int num_pairs, int num_teams, long long xwords, int maxN,
                   int max_nnp, int max_outer, bool need_y, bool need_trace,
-                  bool need_bf16) {
+                  bool need_bf16, int num_groups) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   Layout L{};
   size_t o = 0;
@@ -129,10 +129,10 @@ Layout layout_for(int num_pairs, int num_teams, const Plan& pl, int maxN,
   L.infos = o;
   o = up(o + sizeof(fpfp::DevInfo) * num_pairs);
   L.queue = o;
-  o = up(o + 16);
+  o = up(o + sizeof(unsigned) * (1 + num_groups));
   L.trace = o;
   o = up(o + (need_trace ? sizeof(float) * max_outer : 0));
-  L.xbuf_stride = 2 * fpfp::xbuf_words_per_parity(pl.TR, pl.TC, pl.W, maxN);
+  L.xbuf_stride = 2 * xwords;
   L.xbuf = o;
   o = up(o + sizeof(uint64_t) * L.xbuf_stride * num_teams);
   L.wsT_stride = ((long long)max_nnp + 63) & ~63LL;
@@ -181,37 +181,118 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                    double tol_in, int team_req, bool want_trace,
                    fastpfp_info* infos) {
   HIPCHK(h, hipSetDevice(h->device));
-  int maxN = 1, max_nnp = 1;
-  for (auto& q : pairs) {
-    maxN = std::max(maxN, std::max(q.n, q.np));
-    max_nnp = std::max(max_nnp, q.n * q.np);
+  // ---- team groups: each pair gets the smallest team whose tiles fit it
+  // (or the requested team size); one group per distinct size, largest first
+  const int P = (int)pairs.size();
+  std::vector<Plan> pplan(P);
+  for (int b = 0; b < P; ++b) {
+    const int Nb = std::max(pairs[b].n, pairs[b].np);
+    if (!plan_team(Nb, team_req, &pplan[b]))
+      return fail(h, FASTPFP_ERR_INVALID_ARG,
+                  "team_size %d is not a power of two whose tiles fit N = %d",
+                  team_req, Nb);
   }
-  Plan pl;
-  if (!plan_team(maxN, team_req, &pl))
-    return fail(h, FASTPFP_ERR_INVALID_ARG,
-                "team_size %d is not a power of two whose tiles fit N = %d",
-                team_req, maxN);
   int G = std::min(512, h->occupancy * h->cu_count);
   G -= G % fpfp::kXcds;
-  if (pl.W > G)
+  std::vector<int> sizes;
+  for (auto& q : pplan)
+    if (std::find(sizes.begin(), sizes.end(), q.W) == sizes.end())
+      sizes.push_back(q.W);
+  std::sort(sizes.rbegin(), sizes.rend());
+  if ((int)sizes.size() > fpfp::kMaxGroups)
+    return fail(h, FASTPFP_ERR_UNSUPPORTED, "too many team sizes in a batch");
+  const int NG = (int)sizes.size();
+  std::vector<std::vector<int>> members(NG);
+  std::vector<double> work(NG, 0.0);
+  for (int b = 0; b < P; ++b) {
+    const int g = (int)(std::find(sizes.begin(), sizes.end(), pplan[b].W) -
+                        sizes.begin());
+    members[g].push_back(b);
+    const double Nb = std::max(pairs[b].n, pairs[b].np);
+    work[g] += Nb * Nb;
+  }
+  int need = 0;
+  for (int g = 0; g < NG; ++g) need += sizes[g];
+  if (need > G)
     return fail(h, FASTPFP_ERR_UNSUPPORTED,
-                "N = %d needs %d co-resident workgroups; %d fit", maxN, pl.W, G);
-  const int num_teams = std::max(1, std::min((int)pairs.size(), G / pl.W));
+                "a batch needs %d co-resident workgroups; %d fit", need, G);
+  // workgroups in proportion to work, at least one team per group, at most
+  // one team per pair
+  double wsum = 0.0;
+  for (double w : work) wsum += w;
+  std::vector<int> teams(NG);
+  int used = 0;
+  for (int g = 0; g < NG; ++g) {
+    const int share = (int)((double)G * work[g] / wsum);
+    teams[g] = std::max(1, std::min((int)members[g].size(), share / sizes[g]));
+    used += teams[g] * sizes[g];
+  }
+  while (used > G) {  // trim the group with the most spare teams
+    int best = -1;
+    for (int g = 0; g < NG; ++g)
+      if (teams[g] > 1 && (best < 0 || teams[g] * sizes[g] > teams[best] * sizes[best]))
+        best = g;
+    teams[best]--;
+    used -= sizes[best];
+  }
+  for (bool grew = true; grew;) {  // hand out what is left
+    grew = false;
+    for (int g = 0; g < NG; ++g)
+      if (used + sizes[g] <= G && teams[g] < (int)members[g].size()) {
+        teams[g]++;
+        used += sizes[g];
+        grew = true;
+      }
+  }
+  // pairs in group order, largest first within a group
+  std::vector<int> order;
+  std::vector<fpfp::TeamGroup> grp(NG);
+  int v = 0, tb = 0;
+  long long xwords = 0;
+  int maxN = 1, max_nnp = 1;
+  for (int g = 0; g < NG; ++g) {
+    auto& mem = members[g];
+    std::stable_sort(mem.begin(), mem.end(), [&](int x, int y) {
+      return std::max(pairs[x].n, pairs[x].np) > std::max(pairs[y].n, pairs[y].np);
+    });
+    Plan pl;
+    grid_for(sizes[g], &pl);
+    grp[g].W = pl.W;
+    grp[g].TR = pl.TR;
+    grp[g].TC = pl.TC;
+    grp[g].num_teams = teams[g];
+    grp[g].v_begin = v;
+    grp[g].team_base = tb;
+    grp[g].pair_begin = (int)order.size();
+    int gmaxN = 1;
+    for (int b : mem) {
+      order.push_back(b);
+      gmaxN = std::max(gmaxN, std::max(pairs[b].n, pairs[b].np));
+      max_nnp = std::max(max_nnp, pairs[b].n * pairs[b].np);
+    }
+    grp[g].pair_end = (int)order.size();
+    maxN = std::max(maxN, gmaxN);
+    xwords = std::max(xwords, fpfp::xbuf_words_per_parity(pl.TR, pl.TC, pl.W, gmaxN));
+    v += teams[g] * pl.W;
+    tb += teams[g];
+  }
+  const int num_teams = tb;
   bool need_y = false;
   for (auto& q : pairs) need_y |= (q.Y == nullptr);
   const int max_outer = mode == fpfp::kModeSolve ? p->max_outer : 1;
   const bool need_bf16 = mode == fpfp::kModeSolve &&
                          p->precision == FASTPFP_BF16;
-  Layout lay = layout_for((int)pairs.size(), num_teams, pl, maxN, max_nnp,
-                          max_outer, need_y, want_trace, need_bf16);
+  Layout lay = layout_for(P, num_teams, xwords, maxN, max_nnp, max_outer,
+                          need_y, want_trace, need_bf16, NG);
   fastpfp_status st = ensure_ws(h, lay.total);
   if (st != FASTPFP_OK) return st;
   char* base = (char*)h->ws;
 
-  std::vector<fpfp::PairDesc> pd(pairs.size());
-  for (size_t b = 0; b < pairs.size(); ++b) {
+  std::vector<fpfp::PairDesc> pd(P);
+  for (int k = 0; k < P; ++k) {
+    const int b = order[k];
     const PairIn& q = pairs[b];
-    fpfp::PairDesc& d = pd[b];
+    fpfp::PairDesc& d = pd[k];
     std::memset(&d, 0, sizeof d);
     d.A = q.A;
     d.B = q.B;
@@ -248,11 +329,9 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   fpfp::LaunchDesc L;
   std::memset(&L, 0, sizeof L);
   L.pairs = (const fpfp::PairDesc*)(base + lay.pairs);
-  L.num_pairs = (int)pairs.size();
-  L.W = pl.W;
-  L.TR = pl.TR;
-  L.TC = pl.TC;
-  L.num_teams = num_teams;
+  L.num_pairs = P;
+  L.num_groups = NG;
+  for (int g = 0; g < NG; ++g) L.group[g] = grp[g];
   L.max_N = maxN;
   L.cus_per_xcd = std::max(1, h->cu_count / fpfp::kXcds);
   L.xbuf = (uint64_t*)(base + lay.xbuf);
@@ -269,7 +348,8 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   HIPCHK(h, hipMemcpyAsync(base + lay.pairs, pd.data(),
                            sizeof(fpfp::PairDesc) * pd.size(),
                            hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemsetAsync(base + lay.queue, 0, 16, h->stream));
+  HIPCHK(h, hipMemsetAsync(base + lay.queue, 0,
+                           sizeof(unsigned) * (1 + NG), h->stream));
   HIPCHK(h, hipMemsetAsync(base + lay.infos, 0,
                            sizeof(fpfp::DevInfo) * pd.size(), h->stream));
   HIPCHK(h, hipMemsetAsync(base + lay.xbuf, 0,
@@ -279,12 +359,12 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   HIPCHK(h, fpfp_launch_persistent(&L, G, h->stream));
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   std::vector<fpfp::DevInfo> di(pd.size());
-  unsigned q2[2] = {0, 0};
+  unsigned abort_flag = 0;
   std::vector<float> tr(want_trace ? max_outer : 0);
   HIPCHK(h, hipMemcpyAsync(di.data(), base + lay.infos,
                            sizeof(fpfp::DevInfo) * di.size(),
                            hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(q2, base + lay.queue, sizeof q2,
+  HIPCHK(h, hipMemcpyAsync(&abort_flag, base + lay.queue, sizeof abort_flag,
                            hipMemcpyDeviceToHost, h->stream));
   if (want_trace)
     HIPCHK(h, hipMemcpyAsync(tr.data(), base + lay.trace,
@@ -293,7 +373,7 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   HIPCHK(h, hipStreamSynchronize(h->stream));
   float ms = 0.f;
   HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-  if (q2[1] != 0)
+  if (abort_flag != 0)
     return fail(h, FASTPFP_ERR_TIMEOUT,
                 "a device-side wait exceeded its limit; results are invalid");
   fastpfp_status first = FASTPFP_OK;

@@ -42,12 +42,23 @@ struct PairDesc {
   float lam, alpha, tol_out, tol_in, init_c;
 };
 
-// One persistent launch: teams of W workgroups, each team a TR x TC grid of
-// projection tiles, pulling pairs from a shared queue.
+// Teams of one size within a launch.  Pairs pairs[pair_begin, pair_end) are
+// served by num_teams teams of W workgroups, each team a TR x TC grid of
+// projection tiles; the group's workgroups are virtual indices
+// [v_begin, v_begin + num_teams * W) and its teams are numbered from
+// team_base.
+constexpr int kMaxGroups = 5;
+struct TeamGroup {
+  int W, TR, TC, num_teams, v_begin, team_base, pair_begin, pair_end;
+};
+
+// One persistent launch: up to kMaxGroups team groups pulling pairs from
+// per-group queues.  Per-team workspaces all have the same strides.
 struct LaunchDesc {
   const PairDesc* pairs;
   int num_pairs;
-  int W, TR, TC, num_teams;
+  int num_groups;
+  TeamGroup group[kMaxGroups];
   int max_N;                  // largest N in the launch (workspace sizing)
   int cus_per_xcd;            // compute units per XCD (team placement)
   uint64_t* xbuf;             // exchange words, per team
@@ -58,7 +69,7 @@ struct LaunchDesc {
   long long wsY_stride;
   uint16_t* wsH;              // per team, BF16 products only: A, B, X^T, T
   long long wsH_stride;       // shadows, each Np x Np (Np = N rounded to 128)
-  unsigned* queue;            // [0]: next pair; [1]: abort flag
+  unsigned* queue;            // [0]: abort flag; [1 + g]: group g's next pair
   long long timeout_ticks;    // wall-clock ticks a wait may last
 };
 

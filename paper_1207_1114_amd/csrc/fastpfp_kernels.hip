@@ -693,19 +693,26 @@ fastpfp_persistent(LaunchDesc L) {
   const int cpx = L.cus_per_xcd, b = blockIdx.x;
   const int slot = b / (kXcds * cpx);
   const int v = slot * kXcds * cpx + (b % kXcds) * cpx + (b / kXcds) % cpx;
+  int gi = -1;
+#pragma unroll
+  for (int k = 0; k < kMaxGroups; ++k)
+    if (k < L.num_groups && v >= L.group[k].v_begin &&
+        v < L.group[k].v_begin + L.group[k].num_teams * L.group[k].W)
+      gi = k;
+  if (gi < 0) return;
+  const TeamGroup grp = L.group[gi];
   Team tm;
-  tm.W = L.W;
-  tm.team = v / L.W;
-  tm.rank = v % L.W;
-  if (tm.team >= L.num_teams) return;
-  tm.TR = L.TR;
-  tm.TC = L.TC;
-  tm.tr = tm.rank / L.TC;
-  tm.tc = tm.rank % L.TC;
+  tm.W = grp.W;
+  tm.team = grp.team_base + (v - grp.v_begin) / grp.W;
+  tm.rank = (v - grp.v_begin) % grp.W;
+  tm.TR = grp.TR;
+  tm.TC = grp.TC;
+  tm.tr = tm.rank / grp.TC;
+  tm.tc = tm.rank % grp.TC;
   tm.xb = L.xbuf + (long long)tm.team * L.xbuf_stride;
   tm.par_words = L.xbuf_stride / 2;
   tm.seq = 0;
-  tm.abort_flag = L.queue + 1;
+  tm.abort_flag = L.queue;
   tm.timeout = L.timeout_ticks;
   float* const Tt = L.wsT + (long long)tm.team * L.wsT_stride;
   float* const Yws = L.wsY + (long long)tm.team * L.wsY_stride;
@@ -714,7 +721,8 @@ fastpfp_persistent(LaunchDesc L) {
   for (;;) {
     // ---- next pair: the team leader takes it from the queue and posts it
     if (tm.rank == 0 && tid == 0)
-      sh.wred[0] = __uint_as_float(atomicAdd(L.queue, 1u));
+      sh.wred[0] = __uint_as_float(grp.pair_begin +
+                                   atomicAdd(L.queue + 1 + gi, 1u));
     __syncthreads();
     {
       const float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
@@ -722,7 +730,7 @@ fastpfp_persistent(LaunchDesc L) {
     }
     const unsigned pidx =
         __builtin_amdgcn_readfirstlane(__float_as_uint(sh.scal[0][0]));
-    if (pidx >= (unsigned)L.num_pairs) return;
+    if (pidx >= (unsigned)grp.pair_end) return;
     const PairDesc& pd = L.pairs[pidx];
     const int n = pd.n, np = pd.np, N = pd.N;
     float* const Y = pd.Y ? pd.Y : Yws;

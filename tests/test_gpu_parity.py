@@ -281,3 +281,29 @@ def test_bf16_and_fp32_config2_full_size(env):
     assert res["bf16"]["acc"] >= res["fp32"]["acc"] - 0.005
     assert abs(res["bf16"]["obj"] - res["fp32"]["obj"]) <= \
         1e-3 * abs(res["fp32"]["obj"])
+
+
+def test_mixed_size_batch_uses_team_groups_and_matches_single(env):
+    """Ragged batch spanning two team sizes (N <= 256 -> 1 workgroup,
+    256 < N <= 512 -> 4): every pair equals its own default solve bitwise,
+    in either precision."""
+    torch, F, S = env
+    pairs = [synth.config3_pair(200 + i) for i in range(5)]
+    pairs += [synth.config3_pair(300, n=60, n_extra=3),
+              synth.config3_pair(301, n=300, n_extra=40),
+              synth.config3_pair(302, n=250, n_extra=10)]
+    assert any(max(p.n, p.np_) <= 256 for p in pairs)
+    assert any(max(p.n, p.np_) > 256 for p in pairs)
+    bufs, offs = pack(pairs)
+    for prec in (F.FP32, F.BF16):
+        prm = F.default_params(lambda_=1.0, max_outer=6, max_inner=150,
+                               precision=prec)
+        d = {k: dev(torch, v).view(-1, 1) for k, v in bufs.items()}
+        S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                        d["A"], offs["A"], d["B"], offs["B"], d["K"],
+                        offs["K"], d["X"], offs["X"], prm)
+        Xall = d["X"].cpu().numpy().ravel()
+        for p, o in zip(pairs, offs["X"]):
+            Xb = Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
+            Xs, _, _ = gpu_solve(env, p, prm=prm)
+            np.testing.assert_array_equal(Xb, Xs)
