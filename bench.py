@@ -106,10 +106,10 @@ def cpu_baseline(pair, gpu_infos, passes):
             "seconds_per_pair": t_pair}
 
 
-def ragged_batch(torch, F, O, steps):
+def ragged_batch(torch, F, steps):
     """Config 3: 512 ragged pairs (n ~ U{50..400}, n' = n + U{0..40}) of
     distance-weighted 8-NN point graphs, BF16 products, one launch."""
-    from paper_1207_1114_amd import synth
+    from paper_1207_1114_amd import scores, synth
     pairs = [synth.config3_pair(i) for i in range(512)]
     offs, cur = {k: [] for k in "ABKX"}, {k: 0 for k in "ABKX"}
     bufs = {k: [] for k in "ABKX"}
@@ -137,7 +137,7 @@ def ragged_batch(torch, F, O, steps):
     acc = []
     for p, o in zip(pairs, offs["X"]):
         m, _ = F.discretize(Xall[o:o + p.n * p.np_].reshape(p.n, p.np_))
-        acc.append(O.accuracy(m.astype(np.int64), p.perm))
+        acc.append(scores.accuracy(m, p.perm))
     flops = sum(2.0 * p.n * p.np_ * (p.n + p.np_) * i["outer_iters"]
                 for p, i in zip(pairs, infos))
     return {"value": steps * len(pairs) / dt, "unit": "pairs/s",
@@ -158,7 +158,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_1207_1114_amd import fastpfp as F
-    from oracle import fastpfp_oracle as O
+    from paper_1207_1114_amd import scores
 
     torch.cuda.init()
     pairs, A, B, K, X, offs = make_inputs(torch, args.pairs, args.n)
@@ -193,7 +193,7 @@ def main():
     acc = []
     for i, p in enumerate(pairs):
         m, _ = F.discretize(Xh[i])
-        acc.append(O.accuracy(m.astype(np.int64), p.perm))
+        acc.append(scores.accuracy(m, p.perm))
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -235,14 +235,14 @@ def main():
         torch.cuda.synchronize()
         dt16 = time.perf_counter() - t0
         Xh16 = X.view(args.pairs, n, n).cpu().numpy()
-        acc16 = [O.accuracy(F.discretize(Xh16[i])[0].astype(np.int64),
-                            p.perm) for i, p in enumerate(pairs)]
+        acc16 = [scores.accuracy(F.discretize(Xh16[i])[0], p.perm)
+                 for i, p in enumerate(pairs)]
         out["bf16"] = {"value": args.steps * args.pairs / dt16,
                        "unit": "pairs/s", "tol_outer": BF16_TOL_OUTER,
                        "accuracy_mean": float(np.mean(acc16)),
                        "outer_iters_mean": float(np.mean(
                            [i["outer_iters"] for i in inf16]))}
-        out["config3"] = ragged_batch(torch, F, O, args.steps)
+        out["config3"] = ragged_batch(torch, F, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)
     print(json.dumps(out), flush=True)

@@ -176,6 +176,79 @@ fastpfp_status fastpfp_discretize(int n, int np, const float* X_host, int ldx,
 fastpfp_status fastpfp_get_trace(fastpfp_t h, double* out_host, int cap,
                                  int* count);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper's method: it replaces the
+ * uniform X0 of Algorithm 1 (the paper notes the result depends on the
+ * starting point, Sec. 4.5) by a softmax of similarities between per-node
+ * embeddings, and is trained on fixed points of the plain method.
+ *
+ * Features of node i (48 floats): over i's neighbours k (A[i,k] != 0), a
+ * 16-bin histogram of bin(deg(k)) and one of bin(wdeg(k)), each divided by
+ * deg(i); bin(v) = clip(floor((4 v) / mean), 0, 15) in float64, with deg the
+ * nonzero count and wdeg the sum of a row and mean their average over the
+ * graph (a histogram is zero when its mean is <= 0, both are zero when
+ * deg(i) = 0); then the first min(fdim, 16) attributes, zero-padded to 16.
+ * Network (FASTPFP_WS_NPARAMS floats, in this order, weights row-major
+ * out x in): W1 128x48, b1, W2 128x128, b2, W3 64x128, b3, logtau;
+ * h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), e = W3 h2 + b3.
+ * X0 = softmax of S = E E'^T exp(-logtau) over j for each row i when
+ * n <= n' (rows sum to one), over i for each column j otherwise.
+ * Training loss for a target T (n x n', positive sums along that axis): with
+ * P = T normalised along the same axis, L = -sum P log X0 / min(n, n').
+ * Every call synchronises the handle's stream before it returns.  Results
+ * are deterministic (fixed-order reductions, no floating-point atomics).
+ * ---------------------------------------------------------------------- */
+#define FASTPFP_WS_NPARAMS 31041
+enum { FASTPFP_WS_BF16_WEIGHTS = 1 }; /* round W1..W3 to bfloat16 (RNE) */
+
+/* Copies FASTPFP_WS_NPARAMS host floats (bytes must equal 4x that) to the
+ * handle's device copy and resets the gradient and the Adam moments.
+ * INVALID_ARG if a value is not finite, SHAPE if bytes is wrong. */
+fastpfp_status fastpfp_warmstart_load(fastpfp_t h, const void* blob_host,
+                                      size_t bytes);
+
+/* Copies the parameters and/or the accumulated gradient (either pointer may
+ * be NULL) to the host; count must equal FASTPFP_WS_NPARAMS. */
+fastpfp_status fastpfp_warmstart_get(fastpfp_t h, float* params_host,
+                                     float* grad_host, size_t count);
+
+/* Features of one graph: A (n x n, lda), attributes F (n x fdim, ldf; NULL
+ * iff fdim == 0) -> x_out (n x 48, row pitch ldx >= 48, device). */
+fastpfp_status fastpfp_warmstart_features(fastpfp_t h, int n, const float* A,
+                                          int lda, const float* F, int ldf,
+                                          int fdim, float* x_out, int ldx);
+
+/* Forms X0 (n x n', ldx, device) for the pair (A, B) with attributes F
+ * (n x fdim) and G (n' x fdim), both NULL iff fdim == 0.  flags:
+ * 0 or FASTPFP_WS_BF16_WEIGHTS.  Feed X0 to fastpfp_solve with
+ * init = FASTPFP_INIT_USER.  NUMERIC if an entry of X0 is not finite (the
+ * caller then falls back to the uniform start). */
+fastpfp_status fastpfp_warmstart(fastpfp_t h, int n, int np, const float* A,
+                                 int lda, const float* B, int ldb,
+                                 const float* F, int ldf, const float* G,
+                                 int ldg, int fdim, int flags, float* X0,
+                                 int ldx);
+
+/* Adds the gradient of L for target T (n x n', ldt, device) to the handle's
+ * gradient buffer (float32 weights, no rounding); loss_host (nullable)
+ * receives L.  NUMERIC if a softmax output or a target sum is not finite or
+ * a target sum is <= 0. */
+fastpfp_status fastpfp_warmstart_grad(fastpfp_t h, int n, int np,
+                                      const float* A, int lda, const float* B,
+                                      int ldb, const float* F, int ldf,
+                                      const float* G, int ldg, int fdim,
+                                      const float* T, int ldt,
+                                      double* loss_host);
+
+fastpfp_status fastpfp_warmstart_zero_grad(fastpfp_t h);
+
+/* One Adam step (Kingma & Ba) on the parameters with gradient
+ * grad_scale * (accumulated gradient); the handle counts the steps for the
+ * bias correction.  lr > 0, 0 <= beta < 1, eps > 0. */
+fastpfp_status fastpfp_warmstart_adam(fastpfp_t h, double lr, double beta1,
+                                      double beta2, double eps,
+                                      double grad_scale);
+
 const char* fastpfp_status_string(fastpfp_status s);
 const char* fastpfp_last_error(fastpfp_t h);
 int fastpfp_abi_version(void);

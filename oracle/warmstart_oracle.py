@@ -10,12 +10,15 @@ Definitions (shared with the HIP implementation only through this text):
 * Node features, 48 per node.  deg(k) = number of nonzero entries of row k
   of the adjacency, wdeg(k) = sum of row k; md, mw their means over the graph.
   For node i, over its neighbours k (A_ik != 0):
-    h_deg[b]  = #{k : min(15, floor(4 deg(k) / md)) = b} / deg(i)
-    h_wdeg[b] = #{k : min(15, floor(4 wdeg(k) / mw)) = b} / deg(i)
-  (16 bins each, zero when deg(i) = 0 or the mean is 0), followed by the
-  node's attributes, zero-padded to 16.
+    h_deg[b]  = #{k : clip(floor(4 deg(k) / md), 0, 15) = b} / deg(i)
+    h_wdeg[b] = #{k : clip(floor(4 wdeg(k) / mw), 0, 15) = b} / deg(i)
+  (16 bins each, zero when deg(i) = 0 or the mean is <= 0; the lower clip
+  only matters for a negative weighted degree), followed by the node's
+  attributes, zero-padded to 16.  The bin index is taken in float64 as
+  written: (4 v) / m, then floor.
 * Network: h1 = relu(W1 x + b1) (128), h2 = relu(W2 h1 + b2) (128),
-  e = W3 h2 + b3 (64).
+  e = W3 h2 + b3 (64).  For inference the three weight matrices may be
+  stored in bfloat16 (round to nearest even); biases and tau stay float.
 * X0 = softmax of S = E E'^T / tau (tau = exp(logtau)) along the larger side:
   over j for each row i when n <= n', over i for each column j otherwise, so
   the smaller side sums to one as in the relaxed constraint set (Sec. 4).
@@ -25,6 +28,8 @@ Definitions (shared with the HIP implementation only through this text):
 from __future__ import annotations
 
 import numpy as np
+
+from .fastpfp_oracle import bf16_round
 
 NBINS = 16
 ATTR = 16
@@ -61,7 +66,7 @@ def node_features(A: np.ndarray, F=None) -> np.ndarray:
     def bins(v, m):
         if m <= 0:
             return None
-        return np.minimum(15, np.floor(4.0 * v / m)).astype(np.int64)
+        return np.clip(np.floor(4.0 * v / m), 0, 15).astype(np.int64)
 
     bd, bw = bins(deg, md), bins(wdeg, mw)
     for i in range(n):
@@ -97,7 +102,15 @@ def softmax_x0(E, Ep, logtau):
     return Z / Z.sum(axis=axis, keepdims=True), S, axis
 
 
-def x0(p: dict, A, B, F=None, G=None) -> np.ndarray:
+def bf16_weights(p: dict) -> dict:
+    """The inference copy: W1, W2, W3 rounded to bfloat16."""
+    return {k: (bf16_round(v) if k.startswith("W") else v)
+            for k, v in p.items()}
+
+
+def x0(p: dict, A, B, F=None, G=None, bf16: bool = False) -> np.ndarray:
+    if bf16:
+        p = bf16_weights(p)
     E, _ = mlp_forward(p, node_features(A, F))
     Ep, _ = mlp_forward(p, node_features(B, G))
     return softmax_x0(E, Ep, float(p["logtau"][0]))[0]

@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libfastpfp.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["fastpfp_kernels.hip"]
-CXX_SOURCES = ["fastpfp_api.cpp", "discretize.cpp"]
+HIP_SOURCES = ["fastpfp_kernels.hip", "warmstart.hip"]
+CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp"]
 
 # Packed FP32 VALU instructions stay off: ordinary float code only.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -11,46 +11,16 @@
 #include <vector>
 
 #include "fastpfp.h"
+#include "fastpfp_ctx.h"
 #include "fastpfp_internal.h"
 
 extern "C" hipError_t fpfp_launch_persistent(const fpfp::LaunchDesc* L,
                                              int grid, hipStream_t stream);
 extern "C" hipError_t fpfp_occupancy(int* blocks_per_cu);
 
-struct fastpfp_ctx {
-  int device = 0;
-  int max_n = 0, max_np = 0;
-  hipStream_t stream = nullptr;
-  std::string err;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  int cu_count = 0;
-  int occupancy = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::vector<double> trace;
-};
-
 namespace {
 
-fastpfp_status fail(fastpfp_t h, fastpfp_status s, const char* fmt, ...) {
-  if (h) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    h->err = buf;
-  }
-  return s;
-}
-
-#define HIPCHK(h, call)                                                     \
-  do {                                                                      \
-    hipError_t e_ = (call);                                                 \
-    if (e_ != hipSuccess)                                                   \
-      return fail((h), FASTPFP_ERR_HIP, "%s failed: %s", #call,             \
-                  hipGetErrorString(e_));                                   \
-  } while (0)
+using fpfp::fail;
 
 struct Plan {
   int W, TR, TC;
@@ -473,6 +443,7 @@ fastpfp_status fastpfp_destroy(fastpfp_t h) {
   if (h->ws) (void)hipFree(h->ws);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->warm) fpfp::warm_free(h->warm);
   delete h;
   return FASTPFP_OK;
 }

@@ -30,7 +30,14 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
 EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
            "fastpfp_solve", "fastpfp_solve_batched", "fastpfp_project",
            "fastpfp_discretize", "fastpfp_get_trace", "fastpfp_status_string",
-           "fastpfp_last_error", "fastpfp_abi_version")
+           "fastpfp_last_error", "fastpfp_abi_version",
+           "fastpfp_warmstart_load", "fastpfp_warmstart_get",
+           "fastpfp_warmstart_features", "fastpfp_warmstart",
+           "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
+           "fastpfp_warmstart_adam")
+
+WS_NPARAMS = 31041
+WS_BF16_WEIGHTS = 1
 
 
 class Params(ctypes.Structure):
@@ -77,6 +84,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_project.argtypes = [P, I, P, ctypes.c_double, I, I, L(Info)]
     lib.fastpfp_discretize.argtypes = [I, I, P, I, I, P, L(ctypes.c_double)]
     lib.fastpfp_get_trace.argtypes = [P, P, I, L(I)]
+    D = ctypes.c_double
+    lib.fastpfp_warmstart_load.argtypes = [P, P, ctypes.c_size_t]
+    lib.fastpfp_warmstart_get.argtypes = [P, P, P, ctypes.c_size_t]
+    lib.fastpfp_warmstart_features.argtypes = [P, I, P, I, P, I, I, P, I]
+    lib.fastpfp_warmstart.argtypes = [P, I, I, P, I, P, I, P, I, P, I, I, I,
+                                      P, I]
+    lib.fastpfp_warmstart_grad.argtypes = [P, I, I, P, I, P, I, P, I, P, I,
+                                           I, P, I, L(D)]
+    lib.fastpfp_warmstart_zero_grad.argtypes = [P]
+    lib.fastpfp_warmstart_adam.argtypes = [P, D, D, D, D, D]
     lib.fastpfp_status_string.argtypes = [I]
     lib.fastpfp_status_string.restype = ctypes.c_char_p
     lib.fastpfp_last_error.argtypes = [P]
@@ -84,7 +101,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("fastpfp_params_default", "fastpfp_create",
                  "fastpfp_destroy", "fastpfp_solve", "fastpfp_solve_batched",
                  "fastpfp_project", "fastpfp_discretize",
-                 "fastpfp_get_trace", "fastpfp_abi_version"):
+                 "fastpfp_get_trace", "fastpfp_abi_version",
+                 "fastpfp_warmstart_load", "fastpfp_warmstart_get",
+                 "fastpfp_warmstart_features", "fastpfp_warmstart",
+                 "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
+                 "fastpfp_warmstart_adam"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -207,6 +228,94 @@ class Solver:
         if st != 0:
             self._raise(st)
         return info.as_dict()
+
+    # -- learned warm start ------------------------------------------------
+
+    def warmstart_load(self, params: np.ndarray) -> None:
+        """Loads the FASTPFP_WS_NPARAMS network parameters (host array)."""
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != WS_NPARAMS:
+            raise ValueError(f"need {WS_NPARAMS} parameters, got {p.size}")
+        st = self._lib.fastpfp_warmstart_load(
+            self._h, p.ctypes.data_as(ctypes.c_void_p), p.nbytes)
+        if st != 0:
+            self._raise(st)
+
+    def warmstart_get(self) -> tuple:
+        """(parameters, accumulated gradient) as host float32 arrays."""
+        p = np.zeros(WS_NPARAMS, dtype=np.float32)
+        g = np.zeros(WS_NPARAMS, dtype=np.float32)
+        st = self._lib.fastpfp_warmstart_get(
+            self._h, p.ctypes.data_as(ctypes.c_void_p),
+            g.ctypes.data_as(ctypes.c_void_p), WS_NPARAMS)
+        if st != 0:
+            self._raise(st)
+        return p, g
+
+    @staticmethod
+    def _attr(F):
+        if F is None:
+            return None, 0, 0
+        _check_dev(F, "F")
+        return _ptr(F), F.stride(0), F.shape[1]
+
+    def warmstart_features(self, A, F=None):
+        import torch
+        _check_dev(A, "A")
+        n = A.shape[0]
+        fp, ldf, fdim = self._attr(F)
+        x = torch.empty((n, 48), dtype=torch.float32, device=A.device)
+        st = self._lib.fastpfp_warmstart_features(
+            self._h, n, _ptr(A), A.stride(0), fp, ldf, fdim, _ptr(x), 48)
+        if st != 0:
+            self._raise(st)
+        return x
+
+    def warmstart(self, A, B, F, G, X0, bf16_weights: bool = False) -> None:
+        """Writes the learned X0 into X0 (n x n' device tensor)."""
+        for t, nm in ((A, "A"), (B, "B"), (X0, "X0")):
+            _check_dev(t, nm)
+        fp, ldf, fdim = self._attr(F)
+        gp, ldg, gdim = self._attr(G)
+        if fdim != gdim:
+            raise ValueError("F and G need the same attribute count")
+        st = self._lib.fastpfp_warmstart(
+            self._h, A.shape[0], B.shape[0], _ptr(A), A.stride(0), _ptr(B),
+            B.stride(0), fp, ldf, gp, ldg, fdim,
+            WS_BF16_WEIGHTS if bf16_weights else 0, _ptr(X0), X0.stride(0))
+        if st != 0:
+            self._raise(st)
+
+    def warmstart_grad(self, A, B, F, G, T) -> float:
+        """Accumulates the gradient of the loss against target T; returns
+        the loss."""
+        for t, nm in ((A, "A"), (B, "B"), (T, "T")):
+            _check_dev(t, nm)
+        fp, ldf, fdim = self._attr(F)
+        gp, ldg, gdim = self._attr(G)
+        if fdim != gdim:
+            raise ValueError("F and G need the same attribute count")
+        loss = ctypes.c_double()
+        st = self._lib.fastpfp_warmstart_grad(
+            self._h, A.shape[0], B.shape[0], _ptr(A), A.stride(0), _ptr(B),
+            B.stride(0), fp, ldf, gp, ldg, fdim, _ptr(T), T.stride(0),
+            ctypes.byref(loss))
+        if st != 0:
+            self._raise(st)
+        return loss.value
+
+    def warmstart_zero_grad(self) -> None:
+        st = self._lib.fastpfp_warmstart_zero_grad(self._h)
+        if st != 0:
+            self._raise(st)
+
+    def warmstart_adam(self, lr: float, beta1: float = 0.9,
+                       beta2: float = 0.999, eps: float = 1e-8,
+                       grad_scale: float = 1.0) -> None:
+        st = self._lib.fastpfp_warmstart_adam(self._h, lr, beta1, beta2, eps,
+                                              grad_scale)
+        if st != 0:
+            self._raise(st)
 
     def trace(self, cap: int = 100000) -> np.ndarray:
         out = np.zeros(cap, dtype=np.float64)

@@ -1,0 +1,369 @@
+"""Learned warm start: training it on fixed points of the plain method, and
+solving with it while the uniform start stays the fallback and the judge.
+
+The network and its kernels live in the library (``fastpfp_warmstart*``
+entry points); this module only orchestrates them.
+
+* Runtime (``solve_batched_warm``): X0 of every pair from the network, then
+  Algorithm 1 from that X0 (init = USER).  A pair whose X0 is not finite, or
+  whose solve fails or does not converge, is solved again from the uniform
+  start, so the learned start can only replace the plain one, never lose a
+  pair.
+* Training (``train``): seeded training pairs of the config-4 model
+  (Bernoulli(0.05) graphs, n = n' ~ U{100..500}, noise 0.05, 16-d
+  attributes) are generated in chunks, solved in one batched FP32 launch
+  from the uniform start, and their fixed points X* are the targets of the
+  cross-entropy loss; Adam steps over minibatches run on the GPU through the
+  library's forward and backward kernels.
+* Acceptance (``evaluate``): on held-out pairs, BF16 products with the
+  learned start must reach the plain FP32 run's objective within 1e-3
+  relative and its matching accuracy within 0.5 percentage points.  The
+  verdict is stored with the parameters; ``load_params`` refuses parameters
+  that were not accepted unless asked otherwise.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import fastpfp as F
+from . import scores, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PARAMS_NPY = os.path.join(HERE, "warmstart_params.npy")
+PARAMS_JSON = os.path.join(HERE, "warmstart_params.json")
+
+# With bfloat16 products max|X_{t+1} - X_t| levels off at ~1e-5..1e-4, so
+# runs with BF16 products stop at 1e-4 (float32 runs keep the paper's 1e-6).
+BF16_TOL_OUTER = 1e-4
+OBJ_REL_TOL = 1e-3      # acceptance: objective within 1e-3 relative
+ACC_TOL = 0.005         # acceptance: accuracy within 0.5 percentage points
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-uniform weights, zero biases, tau = 8 (log tau = log 8)."""
+    rng = np.random.default_rng([1207, 1114, 4444, seed])
+    parts = []
+    for shape in ((128, 48), (128,), (128, 128), (128,), (64, 128), (64,)):
+        if len(shape) == 2:
+            b = np.sqrt(6.0 / shape[1])
+            parts.append(rng.uniform(-b, b, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    parts.append(np.array([np.log(8.0)]))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == F.WS_NPARAMS
+    return flat
+
+
+def load_params(require_accepted: bool = True) -> tuple[np.ndarray, dict]:
+    if not os.path.exists(PARAMS_NPY):
+        raise FileNotFoundError(
+            f"{PARAMS_NPY} is missing: train the warm start first "
+            "(python -m paper_1207_1114_amd.warmstart --train)")
+    flat = np.load(PARAMS_NPY, allow_pickle=False).astype(np.float32)
+    meta = {}
+    if os.path.exists(PARAMS_JSON):
+        with open(PARAMS_JSON) as f:
+            meta = json.load(f)
+    if require_accepted and not meta.get("accepted", False):
+        raise RuntimeError("the stored warm-start parameters did not pass "
+                           "the acceptance check against the uniform start")
+    return flat, meta
+
+
+# ---------------------------------------------------------------- batches
+@dataclass
+class Batch:
+    """Pairs packed densely on the device (row pitch = number of columns)."""
+    pairs: list
+    ns: list
+    nps: list
+    A: object
+    B: object
+    K: object
+    Fa: object
+    Gb: object
+    X: object
+    offA: list
+    offB: list
+    offK: list
+    offF: list
+    offG: list
+    fdim: int
+
+    def view(self, buf, off, rows, cols):
+        return buf[off:off + rows * cols].view(rows, cols)
+
+    def x(self, i):
+        return self.view(self.X, self.offK[i], self.ns[i], self.nps[i])
+
+
+def pack(torch, pairs, fdim: int = 16) -> Batch:
+    offs = {k: [] for k in "ABKFG"}
+    cur = {k: 0 for k in "ABKFG"}
+    bufs = {k: [] for k in "ABKFG"}
+    for p in pairs:
+        Fp = p.F if p.F is not None else np.zeros((p.n, fdim))
+        Gp = p.G if p.G is not None else np.zeros((p.np_, fdim))
+        for k, m in (("A", p.A), ("B", p.B), ("K", p.K), ("F", Fp),
+                     ("G", Gp)):
+            offs[k].append(cur[k])
+            bufs[k].append(np.asarray(m, np.float32).ravel())
+            cur[k] += m.size
+    d = {k: torch.from_numpy(np.concatenate(v)).to("cuda")
+         for k, v in bufs.items()}
+    X = torch.zeros_like(d["K"])
+    return Batch(pairs, [p.n for p in pairs], [p.np_ for p in pairs],
+                 d["A"], d["B"], d["K"], d["F"], d["G"], X, offs["A"],
+                 offs["B"], offs["K"], offs["F"], offs["G"], fdim)
+
+
+def solve_batched(S, b: Batch, prm) -> list:
+    return S.solve_batched(b.ns, b.nps, b.A.view(-1, 1), b.offA,
+                           b.B.view(-1, 1), b.offB, b.K.view(-1, 1), b.offK,
+                           b.X.view(-1, 1), b.offK, prm)
+
+
+def _attrs(b: Batch, i):
+    Fa = b.view(b.Fa, b.offF[i], b.ns[i], b.fdim)
+    Gb = b.view(b.Gb, b.offG[i], b.nps[i], b.fdim)
+    return Fa, Gb
+
+
+def warm_x0(S, b: Batch, i: int, bf16_weights: bool = True) -> bool:
+    """Writes the learned X0 of pair i into b.X; False if it is not finite
+    (X0 is then the uniform start)."""
+    A = b.view(b.A, b.offA[i], b.ns[i], b.ns[i])
+    B = b.view(b.B, b.offB[i], b.nps[i], b.nps[i])
+    Fa, Gb = _attrs(b, i)
+    try:
+        S.warmstart(A, B, Fa, Gb, b.x(i), bf16_weights=bf16_weights)
+        return True
+    except F.FastPFPError as e:
+        if e.status != 5:
+            raise
+        b.x(i).fill_(1.0 / max(b.ns[i], b.nps[i]))
+        return False
+
+
+def solve_batched_warm(S, b: Batch, prm, bf16_weights: bool = True
+                       ) -> tuple[list, dict]:
+    """Learned X0 for every pair, one batched solve from it, and a uniform
+    re-solve of every pair the learned start did not bring to convergence.
+    ``prm`` must have init = INIT_USER."""
+    import ctypes
+    torch = _torch()
+    warm_ok = [warm_x0(S, b, i, bf16_weights) for i in range(len(b.ns))]
+    try:
+        infos = solve_batched(S, b, prm)
+    except F.FastPFPError as e:
+        infos = e.infos
+    redo = [i for i, inf in enumerate(infos)
+            if inf["status"] != 0 or not inf["converged"]]
+    if redo:
+        uni = F.Params()
+        ctypes.memmove(ctypes.byref(uni), ctypes.byref(prm),
+                       ctypes.sizeof(F.Params))
+        uni.init = F.INIT_UNIFORM
+        sub = Batch([b.pairs[i] for i in redo], [b.ns[i] for i in redo],
+                    [b.nps[i] for i in redo], b.A, b.B, b.K, b.Fa, b.Gb,
+                    b.X, [b.offA[i] for i in redo], [b.offB[i] for i in redo],
+                    [b.offK[i] for i in redo], [b.offF[i] for i in redo],
+                    [b.offG[i] for i in redo], b.fdim)
+        try:
+            again = solve_batched(S, sub, uni)
+        except F.FastPFPError as e:
+            again = e.infos
+        for i, inf in zip(redo, again):
+            inf["fallback"] = 1
+            infos[i] = inf
+    torch.cuda.synchronize()
+    return infos, {"warm_ok": int(sum(warm_ok)), "fallbacks": len(redo)}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ---------------------------------------------------------------- training
+def train_size(idx: int) -> int:
+    """n = n' of training pair idx, U{100..500}."""
+    return int(np.random.default_rng([1207, 1114, 41, idx]).integers(100, 501))
+
+
+def _gen_train(idx: int):
+    return synth.config4_pair(idx, train_size(idx), train=True)
+
+
+def _generate(indices, workers: int):
+    if workers <= 1:
+        return [_gen_train(i) for i in indices]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.map(_gen_train, indices, chunksize=8)
+
+
+def train(num_pairs: int = 20000, chunk: int = 512, passes: int = 2,
+          minibatch: int = 8, lr: float = 2e-3, lr_end: float = 1e-4,
+          seed: int = 0, workers: int = 16, log=print,
+          init: Optional[np.ndarray] = None) -> tuple[np.ndarray, dict]:
+    """Trains the warm start; returns (parameters, training log)."""
+    torch = _torch()
+    S = F.Solver(512, 512)
+    S.warmstart_load(init if init is not None else init_params(seed))
+    prm = F.default_params(lambda_=1.0)
+    steps_total = max(1, (num_pairs * passes) // minibatch)
+    step = 0
+    hist = []
+    t_start = time.perf_counter()
+    rng = np.random.default_rng([1207, 1114, 42, seed])
+    for c0 in range(0, num_pairs, chunk):
+        idx = list(range(c0, min(num_pairs, c0 + chunk)))
+        t0 = time.perf_counter()
+        pairs = _generate(idx, workers)
+        t_gen = time.perf_counter() - t0
+        b = pack(torch, pairs)
+        t0 = time.perf_counter()
+        infos = solve_batched(S, b, prm)
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        losses = []
+        for _ in range(passes):
+            order = rng.permutation(len(idx))
+            for m0 in range(0, len(order), minibatch):
+                mb = order[m0:m0 + minibatch]
+                S.warmstart_zero_grad()
+                for i in mb:
+                    A = b.view(b.A, b.offA[i], b.ns[i], b.ns[i])
+                    B = b.view(b.B, b.offB[i], b.nps[i], b.nps[i])
+                    Fa, Gb = _attrs(b, i)
+                    losses.append(S.warmstart_grad(A, B, Fa, Gb, b.x(i)))
+                frac = min(1.0, step / steps_total)
+                cur_lr = lr_end + 0.5 * (lr - lr_end) * (1 + np.cos(np.pi * frac))
+                S.warmstart_adam(cur_lr, 0.9, 0.999, 1e-8,
+                                 grad_scale=1.0 / len(mb))
+                step += 1
+        t_train = time.perf_counter() - t0
+        rec = {"pairs": c0 + len(idx), "loss": float(np.mean(losses)),
+               "converged": int(sum(i["converged"] for i in infos)),
+               "gen_s": t_gen, "solve_s": t_solve, "train_s": t_train}
+        hist.append(rec)
+        log(json.dumps(rec))
+        del b
+    params, _ = S.warmstart_get()
+    S.close()
+    return params, {"history": hist, "seconds": time.perf_counter() - t_start,
+                    "num_pairs": num_pairs, "passes": passes,
+                    "minibatch": minibatch, "lr": lr, "lr_end": lr_end,
+                    "chunk": chunk}
+
+
+# -------------------------------------------------------------- acceptance
+def run_plain_and_warm(S, torch, pairs, params: np.ndarray,
+                       plain_prm=None, warm_prm=None, repeats: int = 1
+                       ) -> dict:
+    """Plain FP32 (uniform start) against BF16 + learned start on the same
+    pairs: objectives, accuracies, outer steps and wall time of each."""
+    plain_prm = plain_prm or F.default_params(lambda_=1.0)
+    warm_prm = warm_prm or F.default_params(
+        lambda_=1.0, precision=F.BF16, init=F.INIT_USER,
+        tol_outer=BF16_TOL_OUTER)
+    S.warmstart_load(params)
+    b = pack(torch, pairs)
+    out = {}
+    for name in ("plain", "warm"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            if name == "plain":
+                infos, extra = solve_batched(S, b, plain_prm), {}
+                torch.cuda.synchronize()
+            else:
+                infos, extra = solve_batched_warm(S, b, warm_prm)
+        dt = (time.perf_counter() - t0) / repeats
+        obj, acc = [], []
+        for i, p in enumerate(pairs):
+            m, _ = F.discretize(b.x(i).cpu().numpy())
+            obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
+            acc.append(scores.accuracy(m, p.perm))
+        out[name] = {"objective": obj, "accuracy": acc,
+                     "outer": [i["outer_iters"] for i in infos],
+                     "converged": int(sum(i["converged"] for i in infos)),
+                     "seconds": dt, "pairs_per_s": len(pairs) / dt, **extra}
+    return out
+
+
+def verdict(res: dict) -> dict:
+    op, ow = np.mean(res["plain"]["objective"]), np.mean(res["warm"]["objective"])
+    ap, aw = np.mean(res["plain"]["accuracy"]), np.mean(res["warm"]["accuracy"])
+    ok = bool(ow >= op * (1.0 - OBJ_REL_TOL) and aw >= ap - ACC_TOL)
+    return {"accepted": ok, "objective_plain": float(op),
+            "objective_warm": float(ow),
+            "objective_rel_diff": float((ow - op) / abs(op)),
+            "accuracy_plain": float(ap), "accuracy_warm": float(aw),
+            "outer_plain": float(np.mean(res["plain"]["outer"])),
+            "outer_warm": float(np.mean(res["warm"]["outer"])),
+            "speedup": res["warm"]["pairs_per_s"] / res["plain"]["pairs_per_s"],
+            "fallbacks": res["warm"].get("fallbacks", 0)}
+
+
+def evaluate(params: np.ndarray, sizes=((1000, 16),), log=print) -> dict:
+    """Held-out config-4 model pairs (evaluation seeds) at each (n, count)."""
+    torch = _torch()
+    nmax = max(n for n, _ in sizes)
+    S = F.Solver(nmax, nmax)
+    report = {}
+    for n, count in sizes:
+        pairs = [synth.config4_pair(i, n) for i in range(count)]
+        res = run_plain_and_warm(S, torch, pairs, params)
+        v = verdict(res)
+        report[str(n)] = v
+        log(json.dumps({"n": n, **v}))
+    S.close()
+    report["accepted"] = all(v["accepted"] for k, v in report.items()
+                             if k != "accepted")
+    return report
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--minibatch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--eval", default="1000:16,2000:4",
+                    help="held-out n:count list for the acceptance check")
+    ap.add_argument("--out", default=HERE,
+                    help="directory for warmstart_params.npy/.json")
+    a = ap.parse_args()
+    params, log = train(a.pairs, passes=a.passes, minibatch=a.minibatch,
+                        lr=a.lr, workers=a.workers)
+    sizes = [tuple(int(v) for v in s.split(":")) for s in a.eval.split(",")]
+    rep = evaluate(params, sizes)
+    os.makedirs(a.out, exist_ok=True)
+    np.save(os.path.join(a.out, "warmstart_params.npy"), params)
+    meta = {"accepted": rep["accepted"], "evaluation": rep,
+            "training": {k: v for k, v in log.items() if k != "history"},
+            "loss_first": log["history"][0]["loss"],
+            "loss_last": log["history"][-1]["loss"],
+            "recipe": ("config-4 model training pairs (train seeds), "
+                       "n = n' ~ U{100..500}, targets = FP32 FastPFP fixed "
+                       "points from the uniform start, lambda = 1")}
+    with open(os.path.join(a.out, "warmstart_params.json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps({"accepted": rep["accepted"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

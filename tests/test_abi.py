@@ -55,6 +55,19 @@ def test_null_handle_is_rejected_before_any_device_call(F):
     assert lib.fastpfp_project(None, 4, None, 1e-6, 10, 0,
                                ctypes.byref(info)) == 1
     assert lib.fastpfp_destroy(None) == 1
+    assert lib.fastpfp_warmstart_load(None, None, 0) == 1
+    assert lib.fastpfp_warmstart_get(None, None, None, 0) == 1
+    assert lib.fastpfp_warmstart_zero_grad(None) == 1
+    assert lib.fastpfp_warmstart_adam(None, 1e-3, 0.9, 0.999, 1e-8, 1.0) == 1
+    assert lib.fastpfp_warmstart(None, 4, 4, None, 4, None, 4, None, 0, None,
+                                 0, 0, 0, None, 4) == 1
+
+
+def test_warmstart_parameter_count_matches_oracle(F):
+    from oracle import warmstart_oracle as W
+    txt = open(HEADER).read()
+    m = re.search(r"#define FASTPFP_WS_NPARAMS (\d+)", txt)
+    assert int(m.group(1)) == W.NPARAMS == F.WS_NPARAMS
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (6, 6), (5, 9), (9, 5), (40, 55),

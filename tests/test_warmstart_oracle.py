@@ -47,6 +47,31 @@ def test_features_last_bin_is_open_and_isolated_nodes_are_zero():
     assert W.node_features(A3)[1, 15] == 1.0   # floor(80) clipped to 15
 
 
+def test_negative_weighted_degree_falls_in_bin_zero():
+    """Edge noise can make a row sum negative: its bin clips to 0."""
+    A = np.zeros((4, 4))
+    A[0, 1] = A[1, 0] = -0.5
+    A[2, 3] = A[3, 2] = 2.0
+    A[1, 2] = A[2, 1] = 1.0
+    x = W.node_features(A)
+    # wdeg = -0.5, 0.5, 3, 2 (mean 1.25): node 0's only neighbour (node 1)
+    # has 4*0.5/1.25 = 1.6 -> bin 1; node 1 sees node 0 (-1.6 -> bin 0)
+    # and node 2 (9.6 -> bin 9)
+    assert x[0, 16 + 1] == 1.0
+    assert x[1, 16 + 0] == 0.5 and x[1, 16 + 9] == 0.5
+
+
+def test_bf16_weight_recipe_moves_x0_by_little():
+    rng = np.random.default_rng(8)
+    A = synth.random_weighted_graph(rng, 20, 0.3)
+    B = synth.random_weighted_graph(rng, 24, 0.3)
+    p = W.unpack(W.init_params(0))
+    X, Xb = W.x0(p, A, B), W.x0(p, A, B, bf16=True)
+    assert not np.array_equal(X, Xb)
+    np.testing.assert_allclose(Xb.sum(1), 1.0, atol=1e-12)
+    assert np.abs(X - Xb).max() < 0.05 * X.max()
+
+
 def test_x0_constraint_axis_and_permutation_equivariance():
     rng = np.random.default_rng(3)
     p = W.unpack(W.init_params(1))
