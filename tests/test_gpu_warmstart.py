@@ -221,3 +221,33 @@ def test_a_few_adam_steps_lower_the_loss(env):
         losses.append(S.warmstart_grad(A, B, Fa, Gb, T))
         S.warmstart_adam(3e-3)
     assert losses[-1] < 0.5 * losses[0], losses[::6]
+
+
+def test_batched_x0_equals_single_and_isolates_a_bad_pair(env):
+    torch, F, S = env
+    shapes = [(70, 90), (130, 100), (1, 1), (64, 64), (200, 257)]
+    pairs = [pair(0, n, m, 9 + k) for k, (n, m) in enumerate(shapes)]
+    # pair 3 gets a NaN attribute: only its status may fail
+    Fa3 = pairs[3][2].copy()
+    Fa3[0, 0] = np.nan
+    pairs[3] = (pairs[3][0], pairs[3][1], Fa3, pairs[3][3])
+    S.warmstart_load(params(9))
+    cat = lambda xs: dev(torch, np.concatenate([np.ravel(x) for x in xs]))
+    offs = lambda xs: np.cumsum([0] + [np.size(x) for x in xs[:-1]])
+    As, Bs = [p[0] for p in pairs], [p[1] for p in pairs]
+    Fs, Gs = [p[2] for p in pairs], [p[3] for p in pairs]
+    Xs = [np.zeros(s) for s in shapes]
+    X = cat(Xs)
+    st = S.warmstart_batched([s[0] for s in shapes], [s[1] for s in shapes],
+                             cat(As), offs(As), cat(Bs), offs(Bs), cat(Fs),
+                             offs(Fs), cat(Gs), offs(Gs), 16, X, offs(Xs),
+                             bf16_weights=True)
+    assert st == [0, 0, 0, 5, 0]
+    Xh = X.cpu().numpy()
+    for k, ((n, m), o) in enumerate(zip(shapes, offs(Xs))):
+        if k == 3:
+            continue
+        Xk = torch.zeros(n, m, device="cuda:0")
+        S.warmstart(*(dev(torch, a) for a in pairs[k]), Xk, bf16_weights=True)
+        np.testing.assert_array_equal(Xh[o:o + n * m].reshape(n, m),
+                                      Xk.cpu().numpy())
