@@ -33,9 +33,11 @@ METRIC = ("matched pairs/s at n=1000 (plain FP32 vs BF16+warm start); "
 # as two operations and packed FP32 as two lanes; this build uses neither).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_ENTRY_PASS = 7
-# With bfloat16 products, max|X_{t+1} - X_t| levels off at ~1e-5..1e-4
-# (bfloat16 rounding of X and T); the BF16 legs stop at 1e-4 instead of 1e-6.
-BF16_TOL_OUTER = 1e-4
+# With bfloat16 products max|X_{t+1} - X_t| wanders on a plateau instead of
+# falling below 1e-6 (bfloat16 rounding of X and T moves the fixed point each
+# step); the largest plateau value seen over 32 pairs at n = 1000 was 3.1e-4,
+# so the BF16 legs stop at 5e-4.
+BF16_TOL_OUTER = 5e-4
 
 
 def parse():
@@ -156,7 +158,10 @@ def ragged_batch(torch, F, steps):
 # two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE; profiles/ holds the
 # summaries), each scaled by the factor the same counter reads for a plain
 # 1 GiB copy.  Valid only for the kernel source they were taken on.
-TRAFFIC = None  # {"kernel_sha256": ..., "fetch_kib": ..., "write_kib": ...}
+TRAFFIC = {"kernel_sha256":
+           "011532bf7259969d7f1fb0ff015a758878db925de120a116c514c34ed2db28f6",
+           "fetch_kib": 15932321.3125 * 2.0,   # copy calibration: x 2.0
+           "write_kib": 22082564.71875 * 1.0}  # copy calibration: x 1.0
 
 
 def kernel_sha256() -> str:
@@ -191,8 +196,7 @@ def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc):
     n = max(max(b.ns), max(b.nps))
     S = F.Solver(n, n)
     S.warmstart_load(params)
-    prm = F.default_params(lambda_=1.0, precision=F.BF16, init=F.INIT_USER,
-                           tol_outer=W.BF16_TOL_OUTER)
+    prm = W.warm_params()
     W.solve_batched_warm(S, b, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -38,9 +38,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PARAMS_NPY = os.path.join(HERE, "warmstart_params.npy")
 PARAMS_JSON = os.path.join(HERE, "warmstart_params.json")
 
-# With bfloat16 products max|X_{t+1} - X_t| levels off at ~1e-5..1e-4, so
-# runs with BF16 products stop at 1e-4 (float32 runs keep the paper's 1e-6).
-BF16_TOL_OUTER = 1e-4
+# With bfloat16 products max|X_{t+1} - X_t| wanders on a plateau (up to
+# 3.1e-4 over 32 pairs at n = 1000) instead of falling to the paper's 1e-6,
+# so runs with BF16 products stop at 5e-4; float32 runs keep 1e-6.
+BF16_TOL_OUTER = 5e-4
+# A learned start that has not converged after this many outer steps is
+# abandoned and the pair solved again from the uniform start.
+WARM_MAX_OUTER = 100
 OBJ_REL_TOL = 1e-3      # acceptance: objective within 1e-3 relative
 ACC_TOL = 0.005         # acceptance: accuracy within 0.5 percentage points
 
@@ -178,6 +182,7 @@ def solve_batched_warm(S, b: Batch, prm, bf16_weights: bool = True
         ctypes.memmove(ctypes.byref(uni), ctypes.byref(prm),
                        ctypes.sizeof(F.Params))
         uni.init = F.INIT_UNIFORM
+        uni.max_outer = 1000        # the plain method's own cap
         sub = Batch([b.pairs[i] for i in redo], [b.ns[i] for i in redo],
                     [b.nps[i] for i in redo], b.A, b.B, b.K, b.Fa, b.Gb,
                     b.X, [b.offA[i] for i in redo], [b.offB[i] for i in redo],
@@ -296,6 +301,13 @@ def sharpened(params: np.ndarray, beta: float) -> np.ndarray:
     return p
 
 
+def warm_params():
+    """Solver parameters of the learned-start runs: BF16 products, X0 from
+    the caller, eps1 above the bfloat16 plateau, a short outer cap."""
+    return F.default_params(lambda_=1.0, precision=F.BF16, init=F.INIT_USER,
+                            tol_outer=BF16_TOL_OUTER, max_outer=WARM_MAX_OUTER)
+
+
 def run_plain(S, torch, b: Batch, prm=None, repeats: int = 1) -> dict:
     """The judge: FP32 products from the uniform start."""
     prm = prm or F.default_params(lambda_=1.0)
@@ -310,8 +322,7 @@ def run_plain(S, torch, b: Batch, prm=None, repeats: int = 1) -> dict:
 def run_warm(S, torch, b: Batch, params: np.ndarray, prm=None,
              repeats: int = 1) -> dict:
     """BF16 products from the learned start (uniform fallback per pair)."""
-    prm = prm or F.default_params(lambda_=1.0, precision=F.BF16,
-                                  init=F.INIT_USER, tol_outer=BF16_TOL_OUTER)
+    prm = prm or warm_params()
     S.warmstart_load(params)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -409,16 +420,28 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--init", default=None,
                     help="continue from these raw parameters (.npy)")
+    ap.add_argument("--evaluate-only", default=None,
+                    help="skip training: run the acceptance check on these "
+                         "raw parameters (.npy) and keep their training log "
+                         "from the .json beside them")
     ap.add_argument("--eval", default="1000:16,2000:4",
                     help="held-out n:count list for the acceptance check")
     ap.add_argument("--betas", default="1,2,4,8")
     ap.add_argument("--out", default=HERE,
                     help="directory for warmstart_params.npy/.json")
     a = ap.parse_args()
-    init = (np.load(a.init, allow_pickle=False).astype(np.float32)
-            if a.init else None)
-    raw, log = train(a.pairs, epochs=a.epochs, minibatch=a.minibatch,
-                     lr=a.lr, workers=a.workers, init=init)
+    if a.evaluate_only:
+        raw = np.load(a.evaluate_only, allow_pickle=False).astype(np.float32)
+        with open(os.path.join(os.path.dirname(a.evaluate_only),
+                               "warmstart_params.json")) as f:
+            old = json.load(f)
+        log = {"history": [{"loss": old["loss_first"]},
+                           {"loss": old["loss_last"]}], **old["training"]}
+    else:
+        init = (np.load(a.init, allow_pickle=False).astype(np.float32)
+                if a.init else None)
+        raw, log = train(a.pairs, epochs=a.epochs, minibatch=a.minibatch,
+                         lr=a.lr, workers=a.workers, init=init)
     sizes = [tuple(int(v) for v in s.split(":")) for s in a.eval.split(",")]
     betas = [float(v) for v in a.betas.split(",")]
     rep = evaluate(raw, sizes, betas)

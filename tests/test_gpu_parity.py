@@ -266,7 +266,10 @@ def test_bf16_and_fp32_config2_full_size(env):
     p = synth.config2_pair(0)
     res = {}
     for name, prec in (("fp32", F.FP32), ("bf16", F.BF16)):
-        X, info, _ = gpu_solve(env, p, lambda_=p.lam, precision=prec)
+        # BF16 stops at 5e-4: its eps1 wanders on a plateau below ~3e-4
+        tol = 5e-4 if prec == F.BF16 else 1e-6
+        X, info, _ = gpu_solve(env, p, lambda_=p.lam, precision=prec,
+                               tol_outer=tol)
         m = O.hungarian_discretize(X)
         res[name] = dict(
             err=float(np.abs(X[g["rows"], g["cols"]] - g["xs"]).max()),
