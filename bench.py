@@ -6,12 +6,18 @@ copies with N(0, 0.05^2) edge noise, 16-d attributes, Gaussian K, lambda 1,
 alpha 0.5) to convergence in one persistent launch, inputs resident in HBM.
 Discretisation (Hungarian) runs after the timed region.
 
-Prints one JSON line.  ``roofline`` describes the persistent kernel (the only
-kernel of a step): its inner projection passes are ALU-bound with Y held in
-registers, so ``achieved`` counts 7 float32 operations per entry per pass
-(P1: 2 adds, P2: 1 max, row/column sums: 2 adds, max|dY|: 1 sub + 1 max)
-over the kernel's average launch time measured with HIP events on the
-library's stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample.
+Prints one JSON line.  ``value`` is the plain method: FP32 products, uniform
+start, eps1 = 1e-6.  ``roofline`` describes the persistent kernel (the only
+kernel of a step): its inner projection passes are ALU-bound with Y held on
+chip, so ``achieved`` counts 7 float32 operations per entry per pass (P1: 2
+adds, P2: 1 max, row/column sums: 2 adds, max|dY|: 1 sub + 1 max) over the
+kernel's average launch time measured with HIP events on the library's
+stream; ``traffic`` is the HBM bytes of one launch from counter runs.
+Further legs on the same pairs: ``bf16`` (BF16 products, uniform start),
+``bf16_warmstart`` (BF16 products from the learned start, the batched warm
+start inside the timed step, uniform re-solve of any pair it fails), and
+``config3`` (512 ragged pairs in one launch).  ``cpu_baseline`` times the
+FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
 
