@@ -167,7 +167,8 @@ def ragged_batch(torch, F, steps):
 TRAFFIC = {"kernel_sha256":
            "011532bf7259969d7f1fb0ff015a758878db925de120a116c514c34ed2db28f6",
            "fetch_kib": 15932321.3125 * 2.0,   # copy calibration: x 2.0
-           "write_kib": 22082564.71875 * 1.0}  # copy calibration: x 1.0
+           "write_kib": 22082564.71875 * 1.0,  # copy calibration: x 1.0
+           "team_size": 16}
 
 
 def kernel_sha256() -> str:
@@ -178,16 +179,17 @@ def kernel_sha256() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_bytes(args):
+def traffic_bytes(args, team):
     """HBM bytes per launch (read + written), or None when not measured for
-    this kernel source and workload."""
+    this kernel source, workload and team size."""
     if (TRAFFIC is None or TRAFFIC["kernel_sha256"] != kernel_sha256()
-            or args.pairs != 32 or args.n != 1000 or args.team_size != 0):
+            or args.pairs != 32 or args.n != 1000
+            or team != TRAFFIC["team_size"]):
         return None
     return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
 
 
-def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc):
+def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc, team):
     """BF16 products from the learned warm start on the same pairs as the
     FP32 leg: the timed step is the batched warm start (X0 of every pair),
     the batched solve from it, and the uniform re-solve of any pair the
@@ -203,6 +205,7 @@ def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc):
     S = F.Solver(n, n)
     S.warmstart_load(params)
     prm = W.warm_params()
+    prm.team_size = team
     W.solve_batched_warm(S, b, prm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,7 +255,13 @@ def main():
     pairs, A, B, K, X, offs = make_inputs(torch, args.pairs, args.n)
     n = args.n
     S = F.Solver(n, n)
-    prm = F.default_params(lambda_=1.0, team_size=args.team_size)
+    # team size: the autotuner's pick for this batch unless one is given
+    tuned = None
+    team = args.team_size
+    if team == 0:
+        team, cands = S.autotune(n, args.pairs)
+        tuned = {"chosen": team, "pair_passes_per_s": dict(cands)}
+    prm = F.default_params(lambda_=1.0, team_size=team)
     ns, nps = [n] * args.pairs, [n] * args.pairs
 
     def step():
@@ -296,11 +305,12 @@ def main():
                                 "alpha=0.5, eps1=1e-6, eps2=1e-8, "
                                 "I0=I1=1000, FP32 products"),
                    "pairs_per_step": args.pairs, "n": n, "precision": "fp32",
-                   "team_size": args.team_size or "auto"},
+                   "team_size": team,
+                   "team_size_from": "autotuner" if tuned else "argument"},
         "roofline": {"bound": "alu", "achieved": achieved,
                      "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": traffic_bytes(args),
+                     "traffic": traffic_bytes(args, team),
                      "kernel": "fastpfp_persistent",
                      "avg_launch_ms": kernel_ms,
                      "work_per_launch": (f"{passes} inner passes x {n}^2 "
@@ -311,10 +321,11 @@ def main():
                                            for i in infos])),
         "accuracy_mean": float(np.mean(acc)),
         "converged": int(sum(i["converged"] for i in infos)),
+        "autotune": tuned,
     }
     if not args.no_extra:
         # same workload with BF16 products
-        prm16 = F.default_params(lambda_=1.0, team_size=args.team_size,
+        prm16 = F.default_params(lambda_=1.0, team_size=team,
                                  precision=F.BF16, tol_outer=BF16_TOL_OUTER)
         S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs, prm16)
         torch.cuda.synchronize()
@@ -333,7 +344,7 @@ def main():
                        "outer_iters_mean": float(np.mean(
                            [i["outer_iters"] for i in inf16]))}
         out["bf16_warmstart"] = warm_leg(torch, F, pairs, args.steps, value,
-                                         obj, acc)
+                                         obj, acc, team)
         out["config3"] = ragged_batch(torch, F, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)

@@ -159,6 +159,22 @@ fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
                                int max_inner, int team_size,
                                fastpfp_info* info);
 
+/* Team-size autotuner.  A pair is solved by a team of W workgroups cut
+ * into a TR x TC grid of tiles; larger teams finish one pair faster but
+ * leave fewer teams for the rest of a batch.  For pairs of size
+ * N = max(n, n') in batches of `batch`, this times every power-of-two W from
+ * the smallest whose tiles fit N up to the workgroups the device holds,
+ * running min(batch, workgroups / W) concurrent projections (Algorithm 1,
+ * steps 4-7) of an N x N matrix for `passes` passes each, and returns in
+ * *team_size_out the W with the most pair-passes per second (earliest on
+ * ties).  W_host / rate_host (cap entries each; may be NULL iff cap == 0)
+ * receive every candidate and its rate; *count (nullable) the number
+ * written.  Pass the result as fastpfp_params.team_size.  Allocates and
+ * frees a scratch buffer of min(batch, workgroups / W) N x N floats. */
+fastpfp_status fastpfp_autotune(fastpfp_t h, int N, int batch, int passes,
+                                int* team_size_out, int* W_host,
+                                double* rate_host, int cap, int* count);
+
 /* Discretises a host matrix X (n x n', ldx) into a partial permutation
  * (Sec. 4.5).  method: FASTPFP_HUNGARIAN (maximise sum_i X[i, m(i)] over
  * injective maps of the smaller side) or FASTPFP_GREEDY (repeatedly take

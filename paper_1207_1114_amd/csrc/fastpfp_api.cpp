@@ -538,6 +538,85 @@ fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
   return st;
 }
 
+fastpfp_status fastpfp_autotune(fastpfp_t h, int N, int batch, int passes,
+                                int* team_size_out, int* W_host,
+                                double* rate_host, int cap, int* count) {
+  if (!h || !team_size_out) return FASTPFP_ERR_INVALID_ARG;
+  if (N < 1 || N > std::max(h->max_n, h->max_np))
+    return fail(h, FASTPFP_ERR_SHAPE, "N=%d out of range", N);
+  if (batch < 1 || passes < 1 || passes > 100000 || cap < 0 ||
+      (cap > 0 && (!W_host || !rate_host)))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "bad batch, passes or outputs");
+  HIPCHK(h, hipSetDevice(h->device));
+  Plan pl;
+  if (!plan_team(N, 0, &pl))
+    return fail(h, FASTPFP_ERR_UNSUPPORTED, "N=%d fits no team", N);
+  int G = std::min(512, h->occupancy * h->cu_count);
+  G -= G % fpfp::kXcds;
+  std::vector<int> cand;
+  for (int W = pl.W; W <= std::min(G, fpfp::kMaxTeam); W *= 2) cand.push_back(W);
+  if (cand.empty())
+    return fail(h, FASTPFP_ERR_UNSUPPORTED, "N=%d needs more workgroups", N);
+  // Concurrent projections of a fixed matrix that keeps changing for many
+  // passes (entries of both signs), one copy per concurrent pair.
+  const int conc_max = std::min(batch, G / cand[0]);
+  const size_t NN = (size_t)N * N;
+  std::vector<float> pattern(NN);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j)
+      pattern[(size_t)i * N + j] =
+          (float)((i * 131 + j * 71) % 97) / 97.0f - 0.3f;
+  float* Ybuf = nullptr;
+  if (hipMalloc((void**)&Ybuf, sizeof(float) * NN * conc_max) != hipSuccess)
+    return fail(h, FASTPFP_ERR_NOMEM, "cannot allocate %zu bytes",
+                sizeof(float) * NN * conc_max);
+  fastpfp_status st = FASTPFP_OK;
+  int best = cand[0];
+  double best_rate = -1.0;
+  int k = 0;
+  for (size_t ci = 0; ci < cand.size() && st == FASTPFP_OK; ++ci) {
+    const int W = cand[ci], conc = std::min(batch, G / W);
+    std::vector<PairIn> pairs(conc);
+    std::vector<fastpfp_info> infos(conc);
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && st == FASTPFP_OK; ++rep) {  // warm, timed
+      for (int b = 0; b < conc; ++b) {
+        float* Yb = Ybuf + NN * b;
+        if (hipMemcpyAsync(Yb, pattern.data(), sizeof(float) * NN,
+                           hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+          st = fail(h, FASTPFP_ERR_HIP, "copy of the tuning matrix failed");
+          break;
+        }
+        pairs[b] = PairIn{N, N, nullptr, nullptr, nullptr, nullptr, Yb,
+                          N, N, N, N};
+      }
+      if (st == FASTPFP_OK)
+        st = run(h, pairs, nullptr, fpfp::kModeProject,
+                 rep == 0 ? std::min(passes, 8) : passes, 1e-30, W, false,
+                 infos.data());
+      ms = infos[0].kernel_ms;
+    }
+    if (st != FASTPFP_OK) break;
+    double done = 0.0;  // passes actually run (a pass count below `passes`
+    for (const auto& inf : infos) done += inf.inner_iters_total;  // = early fixed point)
+    const double rate = done / (ms * 1e-3);
+    if (k < cap) {
+      W_host[k] = W;
+      rate_host[k] = rate;
+    }
+    ++k;
+    if (rate > best_rate) {
+      best_rate = rate;
+      best = W;
+    }
+  }
+  (void)hipFree(Ybuf);
+  if (st != FASTPFP_OK) return st;
+  *team_size_out = best;
+  if (count) *count = std::min(k, cap);
+  return FASTPFP_OK;
+}
+
 fastpfp_status fastpfp_get_trace(fastpfp_t h, double* out_host, int cap,
                                  int* count) {
   if (!h || !count || (cap > 0 && !out_host)) return FASTPFP_ERR_INVALID_ARG;

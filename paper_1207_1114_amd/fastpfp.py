@@ -34,7 +34,8 @@ EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
            "fastpfp_warmstart_load", "fastpfp_warmstart_get",
            "fastpfp_warmstart_features", "fastpfp_warmstart",
            "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
-           "fastpfp_warmstart_adam", "fastpfp_warmstart_batched")
+           "fastpfp_warmstart_adam", "fastpfp_warmstart_batched",
+           "fastpfp_autotune")
 
 WS_NPARAMS = 31041
 WS_BF16_WEIGHTS = 1
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                            I, P, I, L(D)]
     lib.fastpfp_warmstart_zero_grad.argtypes = [P]
     lib.fastpfp_warmstart_adam.argtypes = [P, D, D, D, D, D]
+    lib.fastpfp_autotune.argtypes = [P, I, I, I, L(I), P, P, I, L(I)]
     lib.fastpfp_status_string.argtypes = [I]
     lib.fastpfp_status_string.restype = ctypes.c_char_p
     lib.fastpfp_last_error.argtypes = [P]
@@ -107,7 +109,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "fastpfp_warmstart_load", "fastpfp_warmstart_get",
                  "fastpfp_warmstart_features", "fastpfp_warmstart",
                  "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
-                 "fastpfp_warmstart_adam", "fastpfp_warmstart_batched"):
+                 "fastpfp_warmstart_adam", "fastpfp_warmstart_batched",
+                 "fastpfp_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -230,6 +233,21 @@ class Solver:
         if st != 0:
             self._raise(st)
         return info.as_dict()
+
+    def autotune(self, N: int, batch: int, passes: int = 256) -> tuple:
+        """(best team size, [(team size, pair-passes per second), ...])."""
+        cap = 16
+        Ws = np.zeros(cap, dtype=np.int32)
+        rates = np.zeros(cap, dtype=np.float64)
+        best, cnt = ctypes.c_int(), ctypes.c_int()
+        st = self._lib.fastpfp_autotune(
+            self._h, N, batch, passes, ctypes.byref(best),
+            Ws.ctypes.data_as(ctypes.c_void_p),
+            rates.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(cnt))
+        if st != 0:
+            self._raise(st)
+        return best.value, list(zip(Ws[:cnt.value].tolist(),
+                                     rates[:cnt.value].tolist()))
 
     # -- learned warm start ------------------------------------------------
 

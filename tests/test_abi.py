@@ -55,6 +55,8 @@ def test_null_handle_is_rejected_before_any_device_call(F):
     assert lib.fastpfp_project(None, 4, None, 1e-6, 10, 0,
                                ctypes.byref(info)) == 1
     assert lib.fastpfp_destroy(None) == 1
+    assert lib.fastpfp_autotune(None, 100, 1, 8, None, None, None, 0,
+                                None) == 1
     assert lib.fastpfp_warmstart_load(None, None, 0) == 1
     assert lib.fastpfp_warmstart_get(None, None, None, 0) == 1
     assert lib.fastpfp_warmstart_zero_grad(None) == 1

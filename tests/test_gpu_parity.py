@@ -310,3 +310,19 @@ def test_mixed_size_batch_uses_team_groups_and_matches_single(env):
             Xb = Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
             Xs, _, _ = gpu_solve(env, p, prm=prm)
             np.testing.assert_array_equal(Xb, Xs)
+
+
+def test_autotune_times_every_fitting_team_and_its_pick_solves(env):
+    torch, F, S = env
+    best, cands = S.autotune(300, 8, passes=32)
+    Ws = [w for w, _ in cands]
+    # N = 300 needs tiles of <= 256 rows: the smallest team is 2 x 2
+    assert Ws[0] == 4 and Ws == [4 * 2 ** k for k in range(len(Ws))]
+    assert all(r > 0 for _, r in cands)
+    assert best == max(cands, key=lambda c: c[1])[0]
+    p = synth.config3_pair(7, n=300, n_extra=0)
+    X, info, _ = gpu_solve(env, p, lambda_=1.0, team_size=best, max_outer=3,
+                           max_inner=100)
+    assert info["status"] == 0 and info["outer_iters"] == 3
+    ref = O.fastpfp(p.A, p.B, p.K, 1.0, max_outer=3, max_inner=100)
+    assert np.abs(X - ref.X).max() <= 1e-4 * np.abs(ref.X).max()
