@@ -189,6 +189,34 @@ def traffic_bytes(args, team):
     return (TRAFFIC["fetch_kib"] + TRAFFIC["write_kib"]) * 1024.0
 
 
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense
+
+
+def products_leg(torch, F, S, ns, nps, A, B, K, X, offs, team, steps):
+    """The products A X B (step 3) on their own: the same pairs with one
+    inner pass per outer step and 8 outer steps, so the launch is almost all
+    MFMA work; TFLOP/s = 2 n n' (n + n') x outer steps x pairs / launch."""
+    out = {}
+    for name, prec in (("fp32", F.FP32), ("bf16", F.BF16)):
+        prm = F.default_params(lambda_=1.0, team_size=team, precision=prec,
+                               tol_outer=1e-30, max_outer=8, max_inner=1)
+        S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs, prm)
+        ms = []
+        for _ in range(steps):
+            infos = S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X,
+                                    offs, prm)
+            ms.append(infos[0]["kernel_ms"])
+        flops = sum(2.0 * n * m * (n + m) * i["outer_iters"]
+                    for n, m, i in zip(ns, nps, infos))
+        tf = flops / (np.mean(ms) * 1e-3) / 1e12
+        out[name] = {"tflops": tf, "peak": MFMA_PEAK_TFLOPS[name],
+                     "frac": tf / MFMA_PEAK_TFLOPS[name],
+                     "avg_launch_ms": float(np.mean(ms))}
+    out["work"] = ("8 outer steps x 1 inner pass per pair; the pass and the "
+                   "update are inside the time")
+    return out
+
+
 def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc, team):
     """BF16 products from the learned warm start on the same pairs as the
     FP32 leg: the timed step is the batched warm start (X0 of every pair),
@@ -346,6 +374,8 @@ def main():
         out["bf16_warmstart"] = warm_leg(torch, F, pairs, args.steps, value,
                                          obj, acc, team)
         out["config3"] = ragged_batch(torch, F, args.steps)
+        out["products"] = products_leg(torch, F, S, ns, nps, A, B, K, X, offs,
+                                       team, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)
     print(json.dumps(out), flush=True)
