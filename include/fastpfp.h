@@ -121,7 +121,9 @@ fastpfp_status fastpfp_destroy(fastpfp_t h);
  *   info: host pointer, filled on return (may be NULL).
  * Errors: INVALID_ARG for null/ill-formed arguments, SHAPE when n or n'
  * exceed the handle's bounds or ld < columns, NUMERIC on NaN/Inf, TIMEOUT if
- * a device wait gave up; X is unspecified after an error. */
+ * a device wait gave up, UNSUPPORTED when max(n, n') > 4096 (a team of 256
+ * workgroups of 256 x 256 tiles is the largest); X is unspecified after an
+ * error. */
 fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np,
                              const float* A, int lda,
                              const float* B, int ldb,

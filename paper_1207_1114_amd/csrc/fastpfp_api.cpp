@@ -157,10 +157,16 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   std::vector<Plan> pplan(P);
   for (int b = 0; b < P; ++b) {
     const int Nb = std::max(pairs[b].n, pairs[b].np);
-    if (!plan_team(Nb, team_req, &pplan[b]))
+    if (!plan_team(Nb, team_req, &pplan[b])) {
+      if (team_req == 0)
+        return fail(h, FASTPFP_ERR_UNSUPPORTED,
+                    "N = %d exceeds the largest team's tiles (%d x %d)", Nb,
+                    fpfp::kMaxTeamSide * fpfp::kTileRows,
+                    fpfp::kMaxTeamSide * fpfp::kTileCols);
       return fail(h, FASTPFP_ERR_INVALID_ARG,
                   "team_size %d is not a power of two whose tiles fit N = %d",
                   team_req, Nb);
+    }
   }
   int G = std::min(512, h->occupancy * h->cu_count);
   G -= G % fpfp::kXcds;
