@@ -123,3 +123,33 @@ def test_loss_is_minimal_when_softmax_equals_target():
     assert np.abs(W.pack(g)).max() < 1e-12
     ent = -np.sum(X * np.log(X)) / n
     assert abs(loss - ent) < 1e-12
+
+
+def test_network_forward_by_hand():
+    """Hand-set weights: unit 0 = relu(f0 - 0.5), unit 1 = relu(-f0), passed
+    through layer 2 unchanged, and e0 = h0 - 2 h1; every other weight 0.  So
+    S_ij = e0(f_i) e0(g_j) / tau and X0 is its row softmax, computed here
+    directly from the attributes."""
+    p = W.unpack(np.zeros(W.NPARAMS))
+    a0 = 2 * W.NBINS                      # column of attribute 0
+    p["W1"][0, a0], p["b1"][0] = 1.0, -0.5
+    p["W1"][1, a0] = -1.0
+    p["W2"][0, 0] = p["W2"][1, 1] = 1.0
+    p["W3"][0, 0], p["W3"][0, 1] = 1.0, -2.0
+    p["b3"][0] = 0.25
+    p["logtau"][0] = np.log(0.5)
+    rng = np.random.default_rng(9)
+    n, m = 6, 9
+    A = synth.random_weighted_graph(rng, n, 0.5)
+    B = synth.random_weighted_graph(rng, m, 0.5)
+    F, G = rng.normal(size=(n, 3)), rng.normal(size=(m, 3))
+    e = lambda f: (np.maximum(f - 0.5, 0) - 2 * np.maximum(-f, 0) + 0.25)
+    S = np.outer(e(F[:, 0]), e(G[:, 0])) / 0.5
+    want = np.exp(S - S.max(1, keepdims=True))
+    want /= want.sum(1, keepdims=True)
+    np.testing.assert_allclose(W.x0(p, A, B, F, G), want, rtol=1e-12)
+    # transposed orientation: softmax over each column
+    S2 = S.T
+    want2 = np.exp(S2 - S2.max(0, keepdims=True))
+    want2 /= want2.sum(0, keepdims=True)
+    np.testing.assert_allclose(W.x0(p, B, A, G, F), want2, rtol=1e-12)
