@@ -256,17 +256,24 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
       }
       __syncthreads();
       if (k0 + kGK < Kd) fetch(k0 + kGK);
+      // all of this step's operands first, so that the MFMAs issue back to
+      // back instead of each group waiting on its own LDS reads
+      float a0[kGK / 2], a1[kGK / 2], b0[kGK / 2], b1[kGK / 2];
 #pragma unroll
-      for (int kk = 0; kk < kGK; kk += 2) {
-        const int kr = kk + (lane >> 5), col = lane & 31;
-        const float a0 = sh.t.g.lp[kr][wr * 64 + col];
-        const float a1 = sh.t.g.lp[kr][wr * 64 + 32 + col];
-        const float b0 = sh.t.g.lq[kr][wc * 64 + col];
-        const float b1 = sh.t.g.lq[kr][wc * 64 + 32 + col];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      for (int q = 0; q < kGK / 2; ++q) {
+        const int kr = 2 * q + (lane >> 5), col = lane & 31;
+        a0[q] = sh.t.g.lp[kr][wr * 64 + col];
+        a1[q] = sh.t.g.lp[kr][wr * 64 + 32 + col];
+        b0[q] = sh.t.g.lq[kr][wc * 64 + col];
+        b1[q] = sh.t.g.lq[kr][wc * 64 + 32 + col];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the MFMAs
+#pragma unroll
+      for (int q = 0; q < kGK / 2; ++q) {
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[q], b0[q], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[q], b1[q], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[q], b0[q], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[q], b1[q], acc[1][1], 0, 0, 0);
       }
     }
     __syncthreads();
