@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--team-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-passes", type=int, default=300,
+    ap.add_argument("--cpu-passes", type=int, default=4000,
                     help="inner passes of the oracle timed for the baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "

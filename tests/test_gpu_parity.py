@@ -326,3 +326,37 @@ def test_autotune_times_every_fitting_team_and_its_pick_solves(env):
     assert info["status"] == 0 and info["outer_iters"] == 3
     ref = O.fastpfp(p.A, p.B, p.K, 1.0, max_outer=3, max_inner=100)
     assert np.abs(X - ref.X).max() <= 1e-4 * np.abs(ref.X).max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_config3_full_ragged_batch(env, prec):
+    """The 512-pair ragged batch (n ~ U{50..400}, n' = n + U{0..40}) in one
+    launch with the team groups the bench uses, at fixed iteration counts
+    (4 outer steps x 200 passes) so that no stopping test can differ: every
+    pair finite, nonnegative, max X = 1 (step 9); sampled pairs against the
+    oracle (float64 products for FP32, the bfloat16 recipe for BF16)."""
+    torch, F, S = env
+    pairs = [synth.config3_pair(i) for i in range(512)]
+    bufs, offs = pack(pairs)
+    d = {k: dev(torch, v).view(-1, 1) for k, v in bufs.items()}
+    p16 = F.BF16 if prec == "bf16" else F.FP32
+    kw = dict(max_outer=4, max_inner=200, tol_outer=1e-30)
+    prm = F.default_params(lambda_=1.0, precision=p16, **kw)
+    infos = S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                            d["A"], offs["A"], d["B"], offs["B"], d["K"],
+                            offs["K"], d["X"], offs["X"], prm)
+    Xall = d["X"].cpu().numpy().ravel().astype(np.float64)
+    Xs = [Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
+          for p, o in zip(pairs, offs["X"])]
+    for X, inf in zip(Xs, infos):
+        assert inf["status"] == 0 and inf["outer_iters"] == 4
+        assert np.isfinite(X).all() and X.min() >= 0.0
+        assert abs(X.max() - 1.0) <= 1e-6
+    sizes = [max(p.n, p.np_) for p in pairs]
+    for b in (int(np.argmax(sizes)), int(np.argmin(sizes)), 257):
+        p = pairs[b]
+        ref = O.fastpfp(p.A, p.B, p.K, 1.0, eps1=1e-30, max_outer=4,
+                        max_inner=200, products="bf16" if prec == "bf16"
+                        else "fp64")
+        tol = 2.0 ** -8 if prec == "bf16" else 1e-4
+        assert np.abs(Xs[b] - ref.X).max() <= tol * np.abs(ref.X).max(), b
