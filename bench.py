@@ -324,7 +324,8 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "ms_per_step": dt / args.steps * 1e3,
+        "node_matches_per_s": value * n, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": (f"config-1 metric set: {args.pairs} seeded "
