@@ -8,6 +8,10 @@ Host-side bookkeeping on a matching returned by the library's discretisation
   A[i,k] A'[m(i), m(k)] + lambda sum_i K[i, m(i)] (A' symmetric).
 * ``accuracy``: the fraction of nodes with a planted partner that were
   matched to exactly that partner.
+* ``frobenius_error``: eq. (1) without the attribute term, the matching
+  error the paper reports for its unweighted benchmark (Sec. 5.1),
+  ||A - P A' P^T||_F^2 with (P A' P^T)[i,k] = A'[m(i), m(k)] for matched
+  rows and 0 otherwise.
 """
 from __future__ import annotations
 
@@ -29,3 +33,12 @@ def accuracy(match, perm) -> float:
     match, perm = np.asarray(match), np.asarray(perm)
     has = perm >= 0
     return float(np.mean(match[has] == perm[has]))
+
+
+def frobenius_error(A, B, match) -> float:
+    A = np.asarray(A, np.float64)
+    match = np.asarray(match)
+    PBP = np.zeros_like(A)
+    i = np.nonzero(match >= 0)[0]
+    PBP[np.ix_(i, i)] = np.asarray(B, np.float64)[np.ix_(match[i], match[i])]
+    return float(np.sum((A - PBP) ** 2))
