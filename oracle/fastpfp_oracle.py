@@ -14,6 +14,14 @@ matrix products as the only library primitive:
 * ``p2``                  Sec. 4.3, eq. (P2): (Y + |Y|) / 2.
 * ``inner_projection``    Algorithm 1, inner repeat: P1 then P2 until
                           max|Y_{u+1} - Y_u| < eps2 or I1 passes (Sec. 5).
+* ``dykstra_inner``       the projection P_D of eq. (DSP) itself, by Dykstra's
+                          algorithm over the same two sets (P1, then P2 with a
+                          correction term), under the same stopping rule.  The
+                          paper's plain alternation only reaches a nearby
+                          feasible point (Sec. 4.3 invokes von Neumann's lemma,
+                          which is a statement about subspaces, and the set of
+                          P2 is a cone); ``projection="dykstra"`` of
+                          ``fastpfp`` selects this one.
 * ``fastpfp``             Algorithm 1, outer repeat: slack-embedded gradient,
                           inner projection, damped update (eq. fastPFP),
                           max-normalisation (remark after Theorem 1), stop on
@@ -131,25 +139,36 @@ def inner_projection(Y: np.ndarray, eps2: float = DEFAULT_EPS2,
     return InnerResult(Y, max_inner, d, False)
 
 
+def dykstra_inner(Y: np.ndarray, eps2: float = DEFAULT_EPS2,
+                  max_inner: int = DEFAULT_I1) -> InnerResult:
+    """P_D(Y) of eq. (DSP) by Dykstra's algorithm (Boyle & Dykstra, 1986).
+
+    Each pass projects onto the affine set of eq. (PP1) with P1 and onto the
+    cone of eq. (PP2) with P2.  The affine step needs no correction term; the
+    cone step carries q, the part of its input that the last clamp removed:
+    z = P1(x); x' = P2(z + q); q' = z + q - x'.  Stops when
+    max|x' - x| < eps2 or after ``max_inner`` passes, as the plain inner
+    repeat does.
+    """
+    x = np.array(Y, dtype=np.float64)
+    q = np.zeros_like(x)
+    d = np.inf
+    for u in range(1, max_inner + 1):
+        z = p1(x)
+        xn = p2(z + q)
+        q = z + q - xn
+        d = float(np.max(np.abs(xn - x)))
+        x = xn
+        if d < eps2:
+            return InnerResult(x, u, d, True)
+    return InnerResult(x, max_inner, d, False)
+
+
 def dykstra_projection(Y: np.ndarray, tol: float = 1e-13,
                        max_iter: int = 200000) -> np.ndarray:
-    """Exact Frobenius projection onto the doubly stochastic set.
-
-    NOT the paper's method: Dykstra's algorithm (correction term on the cone
-    step only, since the other set is affine).  Used by the tests to check
-    Lemma 1 and Theorem 1, which are statements about the exact projection.
-    """
-    x = Y.copy()
-    q = np.zeros_like(Y)
-    for _ in range(max_iter):
-        z = p1(x)
-        xn = np.maximum(z + q, 0.0)
-        q = z + q - xn
-        if np.max(np.abs(xn - x)) < tol:
-            x = xn
-            break
-        x = xn
-    return x
+    """The exact projection to tight tolerance (tests of Lemma 1 and
+    Theorem 1, which are statements about P_D itself)."""
+    return dykstra_inner(Y, tol, max_iter).Y
 
 
 # --------------------------------------------------------------- the solve
@@ -175,12 +194,18 @@ def fastpfp(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
             max_inner: int = DEFAULT_I1, X0: Optional[np.ndarray] = None,
             Y0: Optional[np.ndarray] = None, normalize_max: bool = True,
             projector: Optional[Callable[[np.ndarray], np.ndarray]] = None,
-            products: str = "fp64") -> SolveResult:
+            products: str = "fp64",
+            projection: str = "alternating") -> SolveResult:
     """Algorithm 1 in float64.
 
-    ``projector`` replaces the inner repeat (tests of Lemma 1 / Theorem 1
-    pass the exact projection); ``Y0`` resumes with a given N x N state.
+    ``projection``: "alternating" is the inner repeat of Algorithm 1;
+    "dykstra" computes eq. (DSP)'s projection with ``dykstra_inner`` under
+    the same eps2 / I1.  ``projector`` replaces the inner repeat by any
+    function (tests of Lemma 1 / Theorem 1); ``Y0`` resumes with a given
+    N x N state.
     """
+    inner = {"alternating": inner_projection,
+             "dykstra": dykstra_inner}[projection]
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     n, np_ = A.shape[0], B.shape[0]
@@ -194,7 +219,7 @@ def fastpfp(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
         Y = Y.copy()
         Y[:n, :np_] = gradient(A, X, B, K, lam, products)  # step 3
         if projector is None:
-            res = inner_projection(Y, eps2, max_inner)   # steps 4-7
+            res = inner(Y, eps2, max_inner)              # steps 4-7
             Y = res.Y
             inner_counts.append(res.iters)
             e2s.append(res.last_delta)

@@ -213,6 +213,49 @@ def test_dykstra_is_exact_projection_and_alternation_is_not():
     assert np.linalg.norm(Y - Alt) >= np.linalg.norm(Y - D) - 1e-12
 
 
+def test_dykstra_inner_matches_the_segment_projection_at_n2():
+    """For N = 2 the doubly stochastic set is the segment
+    {[[t, 1-t], [1-t, t]] : 0 <= t <= 1}; the nearest point to Y in
+    Frobenius norm has t = clip(1/2 + (Y00 + Y11 - Y01 - Y10)/4, 0, 1)."""
+    rng = np.random.default_rng(5)
+    for _ in range(100):
+        Y = rng.normal(size=(2, 2)) * 3
+        t = np.clip(0.5 + (Y[0, 0] + Y[1, 1] - Y[0, 1] - Y[1, 0]) / 4, 0, 1)
+        r = O.dykstra_inner(Y, 1e-14, 100_000)
+        assert r.converged
+        np.testing.assert_allclose(r.Y, [[t, 1 - t], [1 - t, t]], atol=1e-10)
+
+
+def test_dykstra_inner_is_exact_where_the_alternation_is_not():
+    """The Birkhoff certificate holds for Dykstra on every draw; the plain
+    alternation of Algorithm 1 fails it on most of them (its limit is a
+    feasible point, not the nearest one)."""
+    rng = np.random.default_rng(17)
+    alt_fails = 0
+    for _ in range(20):
+        Y = rng.normal(size=(4, 4)) * 2
+        D = O.dykstra_inner(Y, 1e-13, 200_000).Y
+        _birkhoff_certificate(Y, D, 1e-9)
+        Alt = O.inner_projection(Y, 1e-14, 200_000).Y
+        try:
+            _birkhoff_certificate(Y, Alt, 1e-6)
+        except AssertionError:
+            alt_fails += 1
+    assert alt_fails >= 10
+
+
+def test_dykstra_inner_stopping_rule():
+    rng = np.random.default_rng(3)
+    Y = rng.random((12, 12)) * 5
+    r = O.dykstra_inner(Y, 1e-8, 3)
+    assert r.iters == 3 and not r.converged and r.last_delta >= 1e-8
+    r = O.dykstra_inner(Y, 1e-8, 100_000)
+    assert r.converged and r.last_delta < 1e-8
+    assert np.all(r.Y >= 0)
+    np.testing.assert_allclose(r.Y.sum(0), 1.0, atol=1e-6)
+    np.testing.assert_allclose(r.Y.sum(1), 1.0, atol=1e-6)
+
+
 def test_lemma1_nonexpansive_exact_projection():
     rng = np.random.default_rng(19)
     for _ in range(20):
