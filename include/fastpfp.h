@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FASTPFP_ABI_VERSION 1
+#define FASTPFP_ABI_VERSION 2
 
 typedef struct fastpfp_ctx* fastpfp_t;
 
@@ -69,6 +69,16 @@ enum { FASTPFP_FP32 = 0, FASTPFP_BF16 = 1 };
 enum { FASTPFP_INIT_UNIFORM = 0, /* X0 = c 1 1^T                     */
        FASTPFP_INIT_USER = 1 };  /* X0 read from the X buffer        */
 
+/* Inner projection of steps 4-7 (Sec. 4.3).  ALTERNATING is Algorithm 1 as
+ * printed: repeat Y <- P2(P1(Y)).  DYKSTRA computes the projection P_D of
+ * eq. (DSP) that the section defines, by Dykstra's algorithm over the same two
+ * sets (a correction term on the clamp P2; same cost per pass, same
+ * stopping rule on max|dY|).  The plain alternation converges to a feasible
+ * point that is in general not the nearest one; with the paper's start,
+ * subgraph-isomorphism pairs of the synthetic benchmark (Sec. 5.1, node
+ * deletion) that it misses are recovered exactly with DYKSTRA. */
+enum { FASTPFP_PROJ_ALTERNATING = 0, FASTPFP_PROJ_DYKSTRA = 1 };
+
 /* Discretisation (Sec. 4.5) */
 enum { FASTPFP_HUNGARIAN = 0, /* maximum-weight assignment of X         */
        FASTPFP_GREEDY = 1 };  /* the paper's greedy rule (from SM)      */
@@ -85,6 +95,7 @@ typedef struct {
   double init_scale; /* UNIFORM: c; 0 selects c = 1/max(n, n')               */
   int normalize_max; /* 1: step 9 (X /= max X) as in Algorithm 1; 0: skip   */
   int team_size;     /* workgroups per pair; 0 lets the library choose       */
+  int projection;    /* FASTPFP_PROJ_ALTERNATING (default) or _DYKSTRA       */
 } fastpfp_params;
 
 typedef struct {
@@ -100,7 +111,8 @@ typedef struct {
 } fastpfp_info;
 
 /* Fills *p with the defaults: lambda 0, alpha 0.5, eps1 1e-6, eps2 1e-8,
- * I0 = I1 = 1000, FP32, uniform start with c = 1/max(n,n'), step 9 on. */
+ * I0 = I1 = 1000, FP32, uniform start with c = 1/max(n,n'), step 9 on,
+ * the alternating projection. */
 fastpfp_status fastpfp_params_default(fastpfp_params* p);
 
 /* Creates a handle bound to HIP device `device` and to `hip_stream` (a
@@ -154,11 +166,14 @@ fastpfp_status fastpfp_solve_batched(fastpfp_t h, int batch,
 
 /* Runs Algorithm 1's inner repeat (steps 4-7: eqs. P1 then P2 per pass) on
  * one square N x N matrix Y (row pitch N), in place, until
- * max|Y_{u+1} - Y_u| < tol or max_inner passes.  info->inner_iters_total
- * receives the pass count and info->eps2_last the last max|dY|.  Exposed so
- * the projection can be checked and timed on its own. */
+ * max|Y_{u+1} - Y_u| < tol or max_inner passes; with projection =
+ * FASTPFP_PROJ_DYKSTRA, Dykstra's passes instead (Y receives the projection,
+ * the stopping measure is the change of the projected iterate).
+ * info->inner_iters_total receives the pass count and info->eps2_last the
+ * last max|dY|.  Exposed so the projection can be checked and timed on its
+ * own. */
 fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
-                               int max_inner, int team_size,
+                               int max_inner, int team_size, int projection,
                                fastpfp_info* info);
 
 /* Team-size autotuner.  A pair is solved by a team of W workgroups cut

@@ -19,7 +19,14 @@ LIB = os.path.join(HERE, "libfastpfp.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["fastpfp_kernels.hip", "warmstart.hip"]
+# (source, object name, extra defines).  The solver kernel source is compiled
+# once per inner projection so that each kernel sits alone in its code object
+# (sharing one, the out-of-line helpers are register-allocated for both
+# callers and the alternating kernel spills more).
+HIP_SOURCES = [("fastpfp_kernels.hip", "fastpfp_kernels", []),
+               ("fastpfp_kernels.hip", "fastpfp_kernels_dykstra",
+                ["-DFPFP_DYKSTRA_BUILD=1"]),
+               ("warmstart.hip", "warmstart", [])]
 CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp"]
 
 # Packed FP32 VALU instructions stay off: ordinary float code only.
@@ -44,9 +51,9 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     objs = []
-    for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
+    for src, name, defs in HIP_SOURCES:
+        obj = os.path.join(BUILD, name + ".hip.o")
+        _run([hipcc, *HIPCC_FLAGS, *defs, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
               os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in CXX_SOURCES:

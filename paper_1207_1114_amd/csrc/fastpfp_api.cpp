@@ -14,9 +14,15 @@
 #include "fastpfp_ctx.h"
 #include "fastpfp_internal.h"
 
+// The solver kernel in two builds: the alternating inner projection of
+// Algorithm 1 and the exact (Dykstra) one.
 extern "C" hipError_t fpfp_launch_persistent(const fpfp::LaunchDesc* L,
                                              int grid, hipStream_t stream);
 extern "C" hipError_t fpfp_occupancy(int* blocks_per_cu);
+extern "C" hipError_t fpfp_launch_persistent_dykstra(const fpfp::LaunchDesc* L,
+                                                     int grid,
+                                                     hipStream_t stream);
+extern "C" hipError_t fpfp_occupancy_dykstra(int* blocks_per_cu);
 
 namespace {
 
@@ -79,6 +85,10 @@ fastpfp_status check_params(fastpfp_t h, const fastpfp_params* p) {
     return fail(h, FASTPFP_ERR_INVALID_ARG, "init_scale must be finite and >= 0");
   if (p->team_size < 0)
     return fail(h, FASTPFP_ERR_INVALID_ARG, "team_size must be >= 0");
+  if (p->projection != FASTPFP_PROJ_ALTERNATING &&
+      p->projection != FASTPFP_PROJ_DYKSTRA)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown projection %d",
+                p->projection);
   return FASTPFP_OK;
 }
 
@@ -148,7 +158,7 @@ struct PairIn {
 // Plans, launches and waits for one persistent launch over `pairs`.
 fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                    const fastpfp_params* p, int mode, int max_inner,
-                   double tol_in, int team_req, bool want_trace,
+                   double tol_in, int projection, int team_req, bool want_trace,
                    fastpfp_info* infos) {
   HIPCHK(h, hipSetDevice(h->device));
   // ---- team groups: each pair gets the smallest team whose tiles fit it
@@ -332,7 +342,9 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                            sizeof(uint64_t) * lay.xbuf_stride * num_teams,
                            h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
-  HIPCHK(h, fpfp_launch_persistent(&L, G, h->stream));
+  HIPCHK(h, projection == FASTPFP_PROJ_DYKSTRA
+                ? fpfp_launch_persistent_dykstra(&L, G, h->stream)
+                : fpfp_launch_persistent(&L, G, h->stream));
   HIPCHK(h, hipEventRecord(h->ev1, h->stream));
   std::vector<fpfp::DevInfo> di(pd.size());
   unsigned abort_flag = 0;
@@ -414,6 +426,7 @@ fastpfp_status fastpfp_params_default(fastpfp_params* p) {
   p->init_scale = 0.0;
   p->normalize_max = 1;
   p->team_size = 0;
+  p->projection = FASTPFP_PROJ_ALTERNATING;
   return FASTPFP_OK;
 }
 
@@ -426,6 +439,7 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return FASTPFP_ERR_HIP;
   fastpfp_ctx* h = new fastpfp_ctx;
+  int occ_dyk = 0;
   h->device = device;
   h->max_n = max_n;
   h->max_np = max_np;
@@ -434,11 +448,14 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
       hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount,
                             device) != hipSuccess ||
       fpfp_occupancy(&h->occupancy) != hipSuccess ||
+      fpfp_occupancy_dykstra(&occ_dyk) != hipSuccess ||
       hipEventCreate(&h->ev0) != hipSuccess ||
       hipEventCreate(&h->ev1) != hipSuccess) {
     delete h;
     return FASTPFP_ERR_HIP;
   }
+  // launches size their grids for the kernel that fits fewer workgroups
+  h->occupancy = std::min(h->occupancy, occ_dyk);
   *out = h;
   return FASTPFP_OK;
 }
@@ -476,6 +493,7 @@ fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np, const float* A,
   fastpfp_info tmp;
   std::memset(&tmp, 0, sizeof tmp);
   st = run(h, pairs, p, fpfp::kModeSolve, p->max_inner, p->tol_inner,
+           p->projection,
            p->team_size, true, &tmp);
   if (info) *info = tmp;
   return st;
@@ -520,13 +538,14 @@ fastpfp_status fastpfp_solve_batched(fastpfp_t h, int batch, const int* n_host,
   }
   std::vector<fastpfp_info> tmp(batch);
   st = run(h, pairs, p, fpfp::kModeSolve, p->max_inner, p->tol_inner,
+           p->projection,
            p->team_size, false, tmp.data());
   if (infos_host) std::memcpy(infos_host, tmp.data(), sizeof(fastpfp_info) * batch);
   return st;
 }
 
 fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
-                               int max_inner, int team_size,
+                               int max_inner, int team_size, int projection,
                                fastpfp_info* info) {
   if (!h) return FASTPFP_ERR_INVALID_ARG;
   if (N < 1 || N > std::max(h->max_n, h->max_np))
@@ -534,12 +553,16 @@ fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
   if (!Y) return fail(h, FASTPFP_ERR_INVALID_ARG, "Y is NULL");
   if (!(tol > 0.0) || !std::isfinite(tol) || max_inner < 1 || team_size < 0)
     return fail(h, FASTPFP_ERR_INVALID_ARG, "bad tolerance, cap or team size");
+  if (projection != FASTPFP_PROJ_ALTERNATING &&
+      projection != FASTPFP_PROJ_DYKSTRA)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown projection %d",
+                projection);
   std::vector<PairIn> pairs(1);
   pairs[0] = PairIn{N, N, nullptr, nullptr, nullptr, nullptr, Y, N, N, N, N};
   fastpfp_info tmp;
   std::memset(&tmp, 0, sizeof tmp);
   fastpfp_status st = run(h, pairs, nullptr, fpfp::kModeProject, max_inner,
-                          tol, team_size, false, &tmp);
+                          tol, projection, team_size, false, &tmp);
   if (info) *info = tmp;
   return st;
 }
@@ -598,7 +621,8 @@ fastpfp_status fastpfp_autotune(fastpfp_t h, int N, int batch, int passes,
       }
       if (st == FASTPFP_OK)
         st = run(h, pairs, nullptr, fpfp::kModeProject,
-                 rep == 0 ? std::min(passes, 8) : passes, 1e-30, W, false,
+                 rep == 0 ? std::min(passes, 8) : passes, 1e-30,
+                 FASTPFP_PROJ_ALTERNATING, W, false,
                  infos.data());
       ms = infos[0].kernel_ms;
     }

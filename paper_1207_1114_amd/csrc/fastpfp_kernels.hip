@@ -8,6 +8,8 @@
 //   steps 4-7 repeat Y <- max(0, Y + a 1^T + 1 b^T)           (eqs. P1, P2)
 //             with a_i = (1 - r_i)/N + (s - N)/N^2, b_j = (1 - c_j)/N,
 //             r = Y 1, c = Y^T 1, s = 1^T Y 1, until max|dY| < eps2 or I1
+//             (or, in fastpfp_persistent<true>, the exact projection of
+//             eq. (DSP) by Dykstra's algorithm over the same two sets)
 //   step 8    X <- (1 - alpha) X + alpha Y[0:n,0:n']           (eq. fastPFP)
 //   step 9    X <- X / max(X)
 //   until max|dX| < eps1 or I0 steps (Sec. 5, convergence criteria).
@@ -613,6 +615,16 @@ __device__ __forceinline__ void store_tile(const float (&Yr)[kRegRows][kCB],
 
 // Steps 4-7 on the on-chip tile.  Returns false on abort; sets *numeric
 // when a sum or max|dY| is not finite.
+//
+// kDyk selects the exact projection of eq. (DSP) by Dykstra's algorithm in
+// place of Algorithm 1's plain alternation.  Only the clamp P2 needs
+// Dykstra's correction (P1 projects onto an affine set), and the correction
+// q = min(w, 0) and the iterate x = max(w, 0) never overlap, so the tile
+// holds one signed matrix w = z + q (z the P1 output): a pass is
+// w <- w + a 1^T + 1 b^T with a, b from the sums of x, and x = max(w, 0)
+// when the loop ends.  The first pass starts from x = Y itself, as the plain
+// loop does; max|dx| is the stopping measure.
+template <bool kDyk>
 __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
                                            Team& tm, Shared& sh,
                                            const TileGeom& g, int max_inner,
@@ -643,6 +655,9 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
 #pragma unroll
       for (int b = 0; b < kCB; ++b) bv[b] = sh.b_l[pc + 16 * b];
       float dm = 0.f;
+      // Dykstra: floor of the previous iterate max(w, lo); the first pass
+      // compares with the unclamped input
+      const float lo = (kDyk && u == 1) ? -INFINITY : 0.f;
 #pragma unroll
       for (int b = 0; b < kCB; ++b) cs[b] = 0.f;
 #pragma unroll
@@ -652,10 +667,19 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
 #pragma unroll
         for (int b = 0; b < kCB; ++b) {
           const float y = (a < kRegRows) ? Yr[a][b] : FPFP_LY(a, b);
-          const float dd = fmaxf((y + av) + bv[b], 0.f);
-          dm = fmaxf(dm, fabsf(dd - y));
-          r += dd;
-          cs[b] += dd;
+          float dd;
+          if constexpr (kDyk) {
+            dd = (y + av) + bv[b];
+            const float xn = fmaxf(dd, 0.f);
+            dm = fmaxf(dm, fabsf(xn - fmaxf(y, lo)));
+            r += xn;
+            cs[b] += xn;
+          } else {
+            dd = fmaxf((y + av) + bv[b], 0.f);
+            dm = fmaxf(dm, fabsf(dd - y));
+            r += dd;
+            cs[b] += dd;
+          }
           if (a < kRegRows) Yr[a][b] = dd;
           else FPFP_LY(a, b) = dd;
         }
@@ -673,6 +697,16 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
       info.inner_capped++;
     }
   }
+  if constexpr (kDyk) {
+    // the projection is x = max(w, 0)
+#pragma unroll
+    for (int a = 0; a < kRA; ++a)
+#pragma unroll
+      for (int b = 0; b < kCB; ++b) {
+        if (a < kRegRows) Yr[a][b] = fmaxf(Yr[a][b], 0.f);
+        else FPFP_LY(a, b) = fmaxf(FPFP_LY(a, b), 0.f);
+      }
+  }
   info.inner_total += u;
   info.inner_max = max(info.inner_max, u);
   info.eps2 = d;
@@ -689,6 +723,10 @@ __device__ __forceinline__ float wg_max(Shared& sh, float v) {
 }
 
 // --------------------------------------------------------------- the kernel
+// kDyk picks the inner projection: false runs Algorithm 1 as printed (plain
+// alternation of P1 and P2 in steps 4-7), true the exact projection
+// (Dykstra).
+template <bool kDyk>
 __global__ void __launch_bounds__(kThreads, 1)
 fastpfp_persistent(LaunchDesc L) {
   __shared__ Shared sh;
@@ -748,8 +786,8 @@ fastpfp_persistent(LaunchDesc L) {
     if (pd.mode == kModeProject) {
       load_tile(Yr, sh, Y, N, g, pr, pc);
       bool numeric = false;
-      if (!inner_loop(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info, &numeric,
-                      pr, pc))
+      if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
+                            &numeric, pr, pc))
         return;
       store_tile(Yr, sh, Y, N, g, pr, pc);
       info.status = numeric ? 5 : 0;
@@ -847,8 +885,8 @@ fastpfp_persistent(LaunchDesc L) {
         // ---- steps 4-7
         load_tile(Yr, sh, Y, N, g, pr, pc);
         bool numeric = false;
-        if (!inner_loop(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
-                        &numeric, pr, pc))
+        if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
+                              &numeric, pr, pc))
           return;
         if (numeric) {
           info.status = 5;
@@ -936,18 +974,32 @@ fastpfp_persistent(LaunchDesc L) {
   }
 }
 
+// This source is compiled twice (see the build script): without
+// FPFP_DYKSTRA_BUILD it holds the alternating kernel and its launch helpers,
+// with it the Dykstra kernel and helpers suffixed _dykstra.
+#ifdef FPFP_DYKSTRA_BUILD
+constexpr bool kThisDyk = true;
+#define FPFP_ENTRY(name) name##_dykstra
+#else
+constexpr bool kThisDyk = false;
+#define FPFP_ENTRY(name) name
+#endif
+
+template __global__ void fastpfp_persistent<kThisDyk>(LaunchDesc);
+
 }  // namespace fpfp
 
 // Launch helper with C linkage for the host translation unit.
-extern "C" hipError_t fpfp_launch_persistent(const fpfp::LaunchDesc* L,
-                                             int grid, hipStream_t stream) {
+extern "C" hipError_t FPFP_ENTRY(fpfp_launch_persistent)(
+    const fpfp::LaunchDesc* L, int grid, hipStream_t stream) {
   void* args[] = {const_cast<fpfp::LaunchDesc*>(L)};
-  return hipLaunchCooperativeKernel((const void*)fpfp::fastpfp_persistent,
-                                    dim3(grid), dim3(fpfp::kThreads), args, 0,
-                                    stream);
+  return hipLaunchCooperativeKernel(
+      (const void*)fpfp::fastpfp_persistent<fpfp::kThisDyk>, dim3(grid),
+      dim3(fpfp::kThreads), args, 0, stream);
 }
 
-extern "C" hipError_t fpfp_occupancy(int* blocks_per_cu) {
+extern "C" hipError_t FPFP_ENTRY(fpfp_occupancy)(int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, (const void*)fpfp::fastpfp_persistent, fpfp::kThreads, 0);
+      blocks_per_cu, (const void*)fpfp::fastpfp_persistent<fpfp::kThisDyk>,
+      fpfp::kThreads, 0);
 }

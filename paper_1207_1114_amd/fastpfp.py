@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
 FP32, BF16 = 0, 1
 INIT_UNIFORM, INIT_USER = 0, 1
 HUNGARIAN, GREEDY = 0, 1
+ALTERNATING, DYKSTRA = 0, 1
+ABI_VERSION = 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           3: "HIP runtime error", 4: "out of device memory",
@@ -47,7 +49,8 @@ class Params(ctypes.Structure):
                 ("max_outer", ctypes.c_int), ("max_inner", ctypes.c_int),
                 ("precision", ctypes.c_int), ("init", ctypes.c_int),
                 ("init_scale", ctypes.c_double),
-                ("normalize_max", ctypes.c_int), ("team_size", ctypes.c_int)]
+                ("normalize_max", ctypes.c_int), ("team_size", ctypes.c_int),
+                ("projection", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -82,7 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   P, L(Info)]
     lib.fastpfp_solve_batched.argtypes = [P, I, P, P, P, P, P, P, P, P,
                                           L(Params), P, P, P]
-    lib.fastpfp_project.argtypes = [P, I, P, ctypes.c_double, I, I, L(Info)]
+    lib.fastpfp_project.argtypes = [P, I, P, ctypes.c_double, I, I, I,
+                                    L(Info)]
     lib.fastpfp_discretize.argtypes = [I, I, P, I, I, P, L(ctypes.c_double)]
     lib.fastpfp_get_trace.argtypes = [P, P, I, L(I)]
     D = ctypes.c_double
@@ -112,6 +116,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "fastpfp_warmstart_adam", "fastpfp_warmstart_batched",
                  "fastpfp_autotune"):
         getattr(lib, name).restype = ctypes.c_int
+    if lib.fastpfp_abi_version() != ABI_VERSION:
+        raise ImportError(
+            f"{path} has ABI {lib.fastpfp_abi_version()}, this binding needs "
+            f"{ABI_VERSION}; rebuild with `python -m paper_1207_1114_amd.build`")
     return lib
 
 
@@ -223,12 +231,12 @@ class Solver:
             raise err
         return out
 
-    def project(self, Y, tol: float, max_inner: int, team_size: int = 0
-                ) -> dict:
+    def project(self, Y, tol: float, max_inner: int, team_size: int = 0,
+                projection: int = ALTERNATING) -> dict:
         _check_dev(Y, "Y")
         info = Info()
         st = self._lib.fastpfp_project(self._h, Y.shape[0], _ptr(Y), tol,
-                                       max_inner, team_size,
+                                       max_inner, team_size, projection,
                                        ctypes.byref(info))
         if st != 0:
             self._raise(st)

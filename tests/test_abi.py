@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(F):
     for nm in names:
         assert hasattr(lib, nm), nm
     assert set(F.EXPORTS) <= set(names)
-    assert lib.fastpfp_abi_version() == 1
+    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 2
 
 
 def test_status_strings_and_defaults(F):
@@ -43,6 +43,7 @@ def test_status_strings_and_defaults(F):
     p = F.default_params()
     assert (p.alpha, p.tol_outer, p.tol_inner) == (0.5, 1e-6, 1e-8)
     assert (p.max_outer, p.max_inner, p.normalize_max) == (1000, 1000, 1)
+    assert p.projection == F.ALTERNATING
 
 
 def test_null_handle_is_rejected_before_any_device_call(F):
@@ -52,7 +53,7 @@ def test_null_handle_is_rejected_before_any_device_call(F):
     st = lib.fastpfp_solve(None, 4, 4, None, 4, None, 4, None, 4,
                            ctypes.byref(p), None, 4, None, ctypes.byref(info))
     assert st == 1
-    assert lib.fastpfp_project(None, 4, None, 1e-6, 10, 0,
+    assert lib.fastpfp_project(None, 4, None, 1e-6, 10, 0, 0,
                                ctypes.byref(info)) == 1
     assert lib.fastpfp_destroy(None) == 1
     assert lib.fastpfp_autotune(None, 100, 1, 8, None, None, None, 0,
