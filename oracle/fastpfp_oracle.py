@@ -26,6 +26,9 @@ matrix products as the only library primitive:
                           inner projection, damped update (eq. fastPFP),
                           max-normalisation (remark after Theorem 1), stop on
                           max|X_{t+1} - X_t| < eps1 or I0 steps (Sec. 5).
+* ``projected_gradient``  eq. (pg), Sec. 4.2: X <- P_d(X + alpha grad f(X)),
+                          the iteration FastPFP is compared with; same
+                          gradient, projection and stopping rule.
 * ``greedy_discretize``   Sec. 4.5, steps 1-3 (greedy, from SM).
 * ``hungarian_discretize`` the assignment that maximises sum_i X[i, pi(i)],
                           via scipy's linear_sum_assignment (library routine).
@@ -229,6 +232,52 @@ def fastpfp(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
         Xn = (1.0 - alpha) * X + alpha * Y[:n, :np_]     # step 8
         if normalize_max:
             Xn = Xn / Xn.max()                           # step 9
+        e1 = float(np.max(np.abs(Xn - X)))
+        trace.append(e1)
+        X = Xn
+        if e1 < eps1:
+            converged = True
+            break
+    return SolveResult(X, Y, t, inner_counts, trace, converged, e2s)
+
+
+def projected_gradient(A: np.ndarray, B: np.ndarray, K: Optional[np.ndarray],
+                       lam: float, alpha: float, eps1: float = DEFAULT_EPS1,
+                       eps2: float = DEFAULT_EPS2,
+                       max_outer: int = DEFAULT_I0,
+                       max_inner: int = DEFAULT_I1,
+                       X0: Optional[np.ndarray] = None,
+                       normalize_max: bool = False,
+                       projection: str = "alternating",
+                       products: str = "fp64") -> SolveResult:
+    """The Projected Gradient iteration of eq. (pg), Sec. 4.2:
+    X <- P_d(X + alpha grad f(X)), with the same gradient (Sec. 4.1), the same
+    slack embedding and inner projection as ``fastpfp`` (the slack block
+    carries over between steps, as in Algorithm 1) and the same stopping
+    rule.  There is no damping term and, by default, no max-normalisation
+    (eq. (pg) has neither); alpha is the step size and may exceed 1.
+    """
+    inner = {"alternating": inner_projection,
+             "dykstra": dykstra_inner}[projection]
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    n, np_ = A.shape[0], B.shape[0]
+    N = max(n, np_)
+    X = uniform_x0(n, np_) if X0 is None else np.array(X0, dtype=np.float64)
+    Y = np.zeros((N, N))
+    inner_counts, trace, e2s = [], [], []
+    converged = False
+    t = 0
+    for t in range(1, max_outer + 1):
+        Y = Y.copy()
+        Y[:n, :np_] = X + alpha * gradient(A, X, B, K, lam, products)
+        res = inner(Y, eps2, max_inner)
+        Y = res.Y
+        inner_counts.append(res.iters)
+        e2s.append(res.last_delta)
+        Xn = Y[:n, :np_].copy()
+        if normalize_max:
+            Xn = Xn / Xn.max()
         e1 = float(np.max(np.abs(Xn - X)))
         trace.append(e1)
         X = Xn

@@ -480,3 +480,72 @@ def test_bf16_rounding_recipe():
     g16 = O.gradient(A, X, B, None, 0.0, products="bf16")
     rel = np.abs(g16 - g64).max() / np.abs(g64).max()
     assert 1e-5 < rel < 2e-2
+
+
+# ------------------------------------------------ projected gradient (eq. pg)
+@pytest.mark.parametrize("n,m", [(6, 6), (5, 8), (8, 5)])
+@pytest.mark.parametrize("alpha", [0.5, 2.0])
+def test_pg_on_a_linear_objective_reaches_the_optimal_assignment(n, m,
+                                                                 alpha):
+    """A = A' = 0 leaves f(X) = lambda tr(X^T K), linear.  A fixed point of
+    X = P_d(X + alpha K) under the exact projection is a maximiser of
+    <K, X> over the partial doubly stochastic set, whose vertices are the
+    partial permutations: the optimal assignment of K (scipy)."""
+    from scipy.optimize import linear_sum_assignment
+    rng = np.random.default_rng([41, n, m])
+    K = rng.random((n, m))
+    r = O.projected_gradient(np.zeros((n, n)), np.zeros((m, m)), K, 1.0,
+                             alpha, eps1=1e-12, eps2=1e-13,
+                             max_inner=100_000, max_outer=2000,
+                             projection="dykstra")
+    ri, ci = linear_sum_assignment(K, maximize=True)
+    P = np.zeros((n, m))
+    P[ri, ci] = 1.0
+    assert r.converged
+    np.testing.assert_allclose(r.X, P, atol=1e-9)
+
+
+def test_pg_iterates_stay_partial_doubly_stochastic():
+    """Without step 9 every PG iterate is a projection, so it lies in the
+    partial doubly stochastic set (sums 1 on the smaller side, <= 1 on the
+    other, entries >= 0)."""
+    rng = np.random.default_rng(43)
+    n, m = 7, 10
+    A, B = rand_sym(rng, n), rand_sym(rng, m)
+    for t in (1, 3, 6):
+        r = O.projected_gradient(A, B, None, 0.0, 0.7, max_outer=t,
+                                 eps2=1e-13, max_inner=200_000,
+                                 projection="dykstra")
+        X = r.X
+        assert r.outer_iters == t
+        assert np.all(X >= -1e-12)
+        np.testing.assert_allclose(X.sum(1), 1.0, atol=1e-9)
+        assert np.all(X.sum(0) <= 1.0 + 1e-9)
+
+
+def test_pg_is_not_fastpfp_with_unit_alpha():
+    """FastPFP with alpha = 1 projects the gradient alone; PG projects the
+    iterate plus the scaled gradient.  On random graphs their first steps
+    differ; with a zero gradient (A = A' = 0, no K) FastPFP's step is the
+    projection of 0 (every entry 1/n) and PG's the projection of X0."""
+    rng = np.random.default_rng(47)
+    n = 6
+    A, B = rand_sym(rng, n), rand_sym(rng, n)
+    X0 = rng.random((n, n))
+    f = O.fastpfp(A, B, None, 0.0, alpha=1.0, max_outer=1, X0=X0,
+                  normalize_max=False, eps2=1e-13, max_inner=200_000,
+                  projection="dykstra")
+    g = O.projected_gradient(A, B, None, 0.0, 1.0, max_outer=1, X0=X0,
+                             eps2=1e-13, max_inner=200_000,
+                             projection="dykstra")
+    assert np.abs(f.X - g.X).max() > 1e-3
+    Z = np.zeros((n, n))
+    f0 = O.fastpfp(Z, Z, None, 0.0, alpha=1.0, max_outer=1, X0=X0,
+                   normalize_max=False, eps2=1e-13, max_inner=200_000,
+                   projection="dykstra")
+    g0 = O.projected_gradient(Z, Z, None, 0.0, 1.0, max_outer=1, X0=X0,
+                              eps2=1e-13, max_inner=200_000,
+                              projection="dykstra")
+    # gradient 0: FastPFP projects 0 (uniform 1/n), PG projects X0 itself
+    np.testing.assert_allclose(f0.X, np.full((n, n), 1.0 / n), atol=1e-10)
+    np.testing.assert_allclose(g0.X, O.dykstra_projection(X0), atol=1e-10)
