@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FASTPFP_ABI_VERSION 2
+#define FASTPFP_ABI_VERSION 3
 
 typedef struct fastpfp_ctx* fastpfp_t;
 
@@ -79,13 +79,22 @@ enum { FASTPFP_INIT_UNIFORM = 0, /* X0 = c 1 1^T                     */
  * deletion) that it misses are recovered exactly with DYKSTRA. */
 enum { FASTPFP_PROJ_ALTERNATING = 0, FASTPFP_PROJ_DYKSTRA = 1 };
 
+/* Iteration of the outer loop.  FASTPFP is Algorithm 1 (eq. fastPFP):
+ * X <- (1 - alpha) X + alpha P_d(grad f(X)).  PG is the Projected Gradient
+ * iteration the paper compares it with (eq. pg, Sec. 4.2):
+ * X <- P_d(X + alpha grad f(X)), alpha the step size (any finite value > 0),
+ * with the same gradient, projection, stopping rule and step 9 flag (eq. pg
+ * has no step 9: pass normalize_max = 0 for it as printed). */
+enum { FASTPFP_METHOD_FASTPFP = 0, FASTPFP_METHOD_PG = 1 };
+
 /* Discretisation (Sec. 4.5) */
 enum { FASTPFP_HUNGARIAN = 0, /* maximum-weight assignment of X         */
        FASTPFP_GREEDY = 1 };  /* the paper's greedy rule (from SM)      */
 
 typedef struct {
   double lambda;     /* >= 0, weight of K in eq. (3); K may be NULL iff 0    */
-  double alpha;      /* step size of eq. fastPFP, in (0, 1]; paper uses 0.5  */
+  double alpha;      /* step size of eq. fastPFP, in (0, 1]; paper uses 0.5;
+                        PG: the step of eq. pg, any finite value > 0        */
   double tol_outer;  /* eps1 > 0: stop when max|X_{t+1} - X_t| < eps1        */
   double tol_inner;  /* eps2 > 0: inner stop when max|Y_{u+1} - Y_u| < eps2  */
   int max_outer;     /* I0 >= 1: cap on outer steps                          */
@@ -96,6 +105,7 @@ typedef struct {
   int normalize_max; /* 1: step 9 (X /= max X) as in Algorithm 1; 0: skip   */
   int team_size;     /* workgroups per pair; 0 lets the library choose       */
   int projection;    /* FASTPFP_PROJ_ALTERNATING (default) or _DYKSTRA       */
+  int method;        /* FASTPFP_METHOD_FASTPFP (default) or _PG              */
 } fastpfp_params;
 
 typedef struct {
@@ -112,7 +122,7 @@ typedef struct {
 
 /* Fills *p with the defaults: lambda 0, alpha 0.5, eps1 1e-6, eps2 1e-8,
  * I0 = I1 = 1000, FP32, uniform start with c = 1/max(n,n'), step 9 on,
- * the alternating projection. */
+ * the alternating projection, the FastPFP iteration. */
 fastpfp_status fastpfp_params_default(fastpfp_params* p);
 
 /* Creates a handle bound to HIP device `device` and to `hip_stream` (a

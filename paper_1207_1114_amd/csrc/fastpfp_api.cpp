@@ -70,8 +70,13 @@ fastpfp_status check_params(fastpfp_t h, const fastpfp_params* p) {
   if (!p) return fail(h, FASTPFP_ERR_INVALID_ARG, "params is NULL");
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda))
     return fail(h, FASTPFP_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-  if (!(p->alpha > 0.0 && p->alpha <= 1.0))
+  if (p->method != FASTPFP_METHOD_FASTPFP && p->method != FASTPFP_METHOD_PG)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown method %d", p->method);
+  if (p->method == FASTPFP_METHOD_FASTPFP && !(p->alpha > 0.0 && p->alpha <= 1.0))
     return fail(h, FASTPFP_ERR_INVALID_ARG, "alpha must lie in (0, 1]");
+  if (p->method == FASTPFP_METHOD_PG &&
+      !(p->alpha > 0.0 && std::isfinite(p->alpha)))
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "the PG step must be finite and > 0");
   if (!(p->tol_outer > 0.0) || !std::isfinite(p->tol_outer) ||
       !(p->tol_inner > 0.0) || !std::isfinite(p->tol_inner))
     return fail(h, FASTPFP_ERR_INVALID_ARG, "tolerances must be finite and > 0");
@@ -304,7 +309,11 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
       d.max_outer = p->max_outer;
       d.precision = p->precision;
       d.lam = (float)p->lambda;
-      d.alpha = (float)p->alpha;
+      // Projected Gradient: step 3 forms X + alpha * gradient and step 8
+      // takes the projection undamped
+      const bool pg = p->method == FASTPFP_METHOD_PG;
+      d.alpha = pg ? 1.0f : (float)p->alpha;
+      d.pg_step = pg ? (float)p->alpha : 0.0f;
       d.tol_out = (float)p->tol_outer;
       d.init_c = (float)(p->init_scale > 0.0 ? p->init_scale
                                              : 1.0 / (double)d.N);
@@ -427,6 +436,7 @@ fastpfp_status fastpfp_params_default(fastpfp_params* p) {
   p->normalize_max = 1;
   p->team_size = 0;
   p->projection = FASTPFP_PROJ_ALTERNATING;
+  p->method = FASTPFP_METHOD_FASTPFP;
   return FASTPFP_OK;
 }
 

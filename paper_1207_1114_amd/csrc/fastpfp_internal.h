@@ -40,6 +40,7 @@ struct PairDesc {
   int n, np, N, lda, ldb, ldk, ldx;
   int mode, init_user, y_user, normalize, max_outer, max_inner, precision;
   float lam, alpha, tol_out, tol_in, init_c;
+  float pg_step;   // Projected Gradient step (eq. pg); 0 for FastPFP
 };
 
 // Teams of one size within a launch.  Pairs pairs[pair_begin, pair_end) are

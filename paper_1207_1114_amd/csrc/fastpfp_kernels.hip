@@ -11,6 +11,8 @@
 //             (or, in fastpfp_persistent<true>, the exact projection of
 //             eq. (DSP) by Dykstra's algorithm over the same two sets)
 //   step 8    X <- (1 - alpha) X + alpha Y[0:n,0:n']           (eq. fastPFP)
+//             (a Projected Gradient pair, eq. pg, writes X + step * gradient
+//             in step 3 and takes alpha = 1 here)
 //   step 9    X <- X / max(X)
 //   until max|dX| < eps1 or I0 steps (Sec. 5, convergence criteria).
 //
@@ -855,10 +857,15 @@ fastpfp_persistent(LaunchDesc L) {
           const float* const Kp = pd.K;
           const int ldk = pd.ldk, NN = N, nn = n, npp = np;
           float* const Yw = Y;
+          // Projected Gradient (eq. pg): Y = X + step * gradient
+          const float step = pd.pg_step;
+          const float* const Xp = step != 0.f ? X : nullptr;
+          const int ldxp = ldx;
           auto out = [=](int m, int c, float val) {
             if (m < nn && c < npp) {
               float yv = val;
               if (Kp) yv += lam * Kp[(long long)m * ldk + c];
+              if (Xp) yv = Xp[(long long)m * ldxp + c] + step * yv;
               Yw[(long long)m * NN + c] = yv;
             }
           };

@@ -22,7 +22,8 @@ FP32, BF16 = 0, 1
 INIT_UNIFORM, INIT_USER = 0, 1
 HUNGARIAN, GREEDY = 0, 1
 ALTERNATING, DYKSTRA = 0, 1
-ABI_VERSION = 2
+METHOD_FASTPFP, METHOD_PG = 0, 1
+ABI_VERSION = 3
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           3: "HIP runtime error", 4: "out of device memory",
@@ -50,7 +51,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("init", ctypes.c_int),
                 ("init_scale", ctypes.c_double),
                 ("normalize_max", ctypes.c_int), ("team_size", ctypes.c_int),
-                ("projection", ctypes.c_int)]
+                ("projection", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

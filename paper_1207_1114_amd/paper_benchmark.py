@@ -17,7 +17,12 @@ which the paper reports for FastPFP in all four cases) and the fraction of
 nodes matched to their planted partner.
 
     python -m paper_1207_1114_amd.paper_benchmark [--sizes 100,500,1000,1500]
-        [--pairs 4] [--projection alternating|dykstra|both]
+        [--pairs 4] [--cases abcd] [--projection alternating|dykstra|both]
+        [--method fastpfp|pg] [--alpha 0.5[,0.7,...]]
+
+The same runner gives the step-size study of Sec. 6.2 (FastPFP with
+alpha in [0.1, 1]) and the Projected Gradient comparison of Sec. 5
+(--method pg, alpha its step size) on these synthetic pairs.
 """
 from __future__ import annotations
 
@@ -31,6 +36,7 @@ from . import scores, synth
 CASES = {"a": (False, False), "b": (True, False), "c": (False, True),
          "d": (True, True)}
 SIZES = (100, 300, 500, 700, 900, 1100, 1300, 1500)
+NUMERIC = 5  # FASTPFP_ERR_NUMERIC
 
 
 def pairs_for(n: int, case: str, count: int) -> list:
@@ -57,21 +63,33 @@ def solve(S, torch, pairs, prm_kw: dict | None = None):
     assert all((p.n, p.np_) == (n0, m0) for p in pairs)
     kw = dict(lambda_=0.0, init_scale=1.0 / (n0 * m0))
     kw.update(prm_kw or {})
-    infos = S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
-                            d["A"], offs["A"], d["B"], offs["B"], None,
-                            None, d["X"], offs["X"], F.default_params(**kw))
+    try:
+        infos = S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                                d["A"], offs["A"], d["B"], offs["B"], None,
+                                None, d["X"], offs["X"],
+                                F.default_params(**kw))
+    except F.FastPFPError as e:
+        # pairs whose iterates overflowed (status NUMERIC) are reported as
+        # failed; the rest of the batch is complete
+        if e.status != NUMERIC or not hasattr(e, "infos"):
+            raise
+        infos = e.infos
     Xall = d["X"].cpu().numpy().ravel().astype(np.float64)
     Xs = [Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
           for p, o in zip(pairs, offs["X"])]
     return Xs, infos
 
 
-def evaluate(pairs, Xs, method: int = F.HUNGARIAN) -> dict:
+def evaluate(pairs, Xs, method: int = F.HUNGARIAN, infos=None) -> dict:
     """Scores of the discretised results; `solved` counts pairs whose error
-    is at most the planted correspondence's."""
+    is at most the planted correspondence's.  A pair whose solve ended with
+    non-finite values scores as no match (every node unmatched)."""
     diff, acc = [], []
-    for p, X in zip(pairs, Xs):
-        m, _ = F.discretize(X, method)
+    for k, (p, X) in enumerate(zip(pairs, Xs)):
+        if infos is not None and infos[k]["status"] != 0:
+            m = np.full(p.n, -1, dtype=np.int32)
+        else:
+            m, _ = F.discretize(X, method)
         diff.append(scores.frobenius_error(p.A, p.B, m)
                     - scores.frobenius_error(p.A, p.B, p.perm))
         acc.append(scores.accuracy(m, p.perm))
@@ -82,26 +100,36 @@ def evaluate(pairs, Xs, method: int = F.HUNGARIAN) -> dict:
 
 
 PROJECTIONS = {"alternating": F.ALTERNATING, "dykstra": F.DYKSTRA}
+METHODS = {"fastpfp": F.METHOD_FASTPFP, "pg": F.METHOD_PG}
 
 
 def run(sizes=SIZES, count: int = 4, projection: str = "alternating",
+        method: str = "fastpfp", alpha: float = 0.5, cases=tuple(CASES),
         log=print) -> list:
+    """One batched launch per (n, case).  method "pg" runs eq. (pg) with
+    step alpha and no step 9; "fastpfp" runs Algorithm 1 with damping
+    alpha."""
     import torch
     S = F.Solver(max(sizes), max(sizes))
+    prm = {"projection": PROJECTIONS[projection], "method": METHODS[method],
+           "alpha": alpha}
+    if method == "pg":
+        prm["normalize_max"] = 0
     rows = []
     for n in sizes:
-        for case in CASES:
+        for case in cases:
             pairs = pairs_for(n, case, count)
-            Xs, infos = solve(S, torch, pairs,
-                              {"projection": PROJECTIONS[projection]})
-            row = {"n": n, "case": case, "pairs": count,
-                   "projection": projection,
+            Xs, infos = solve(S, torch, pairs, prm)
+            row = {"n": n, "case": case, "pairs": count, "method": method,
+                   "alpha": alpha, "projection": projection,
                    "ms_per_pair": infos[0]["kernel_ms"] / count,
                    "outer_mean": float(np.mean([i["outer_iters"]
                                                 for i in infos])),
                    "converged": int(sum(i["converged"] for i in infos)),
-                   "hungarian": evaluate(pairs, Xs),
-                   "greedy": evaluate(pairs, Xs, F.GREEDY)}
+                   "non_finite": int(sum(i["status"] == NUMERIC
+                                         for i in infos)),
+                   "hungarian": evaluate(pairs, Xs, F.HUNGARIAN, infos),
+                   "greedy": evaluate(pairs, Xs, F.GREEDY, infos)}
             rows.append(row)
             log(json.dumps(row))
     S.close()
@@ -113,11 +141,17 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sizes", default=",".join(str(s) for s in SIZES))
     ap.add_argument("--pairs", type=int, default=4)
+    ap.add_argument("--cases", default="abcd")
     ap.add_argument("--projection", choices=[*PROJECTIONS, "both"],
                     default="both")
+    ap.add_argument("--method", choices=list(METHODS), default="fastpfp")
+    ap.add_argument("--alpha", default="0.5",
+                    help="FastPFP damping or PG step; a comma list sweeps")
     a = ap.parse_args()
+    sizes = tuple(int(v) for v in a.sizes.split(","))
     for proj in (PROJECTIONS if a.projection == "both" else [a.projection]):
-        run(tuple(int(s) for s in a.sizes.split(",")), a.pairs, proj)
+        for alpha in (float(v) for v in a.alpha.split(",")):
+            run(sizes, a.pairs, proj, a.method, alpha, tuple(a.cases))
 
 
 if __name__ == "__main__":

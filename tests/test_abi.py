@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(F):
     for nm in names:
         assert hasattr(lib, nm), nm
     assert set(F.EXPORTS) <= set(names)
-    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 2
+    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 3
 
 
 def test_status_strings_and_defaults(F):
@@ -43,7 +43,7 @@ def test_status_strings_and_defaults(F):
     p = F.default_params()
     assert (p.alpha, p.tol_outer, p.tol_inner) == (0.5, 1e-6, 1e-8)
     assert (p.max_outer, p.max_inner, p.normalize_max) == (1000, 1000, 1)
-    assert p.projection == F.ALTERNATING
+    assert p.projection == F.ALTERNATING and p.method == F.METHOD_FASTPFP
 
 
 def test_null_handle_is_rejected_before_any_device_call(F):
