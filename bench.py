@@ -260,6 +260,37 @@ def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc, team):
             "accepted_on_heldout": bool(meta.get("accepted"))}
 
 
+def discretize_leg(torch, F, S, Xh, X, offs, n, steps):
+    """The paper's greedy discretisation (Sec. 4.5) of the batch's results
+    on the device, one call for all pairs, against the host greedy and
+    Hungarian discretisers on the same matrices."""
+    b = Xh.shape[0]
+    match = torch.empty(b * n, dtype=torch.int32, device="cuda:0")
+    offm = [i * n for i in range(b)]
+    args = ([n] * b, [n] * b, X.view(-1), offs, match, offm)
+    S.discretize_greedy_batched(*args)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S.discretize_greedy_batched(*args)
+    dev_ms = (time.perf_counter() - t0) / steps * 1e3
+    got = match.view(b, n).cpu().numpy()
+    t0 = time.perf_counter()
+    host = [F.discretize(Xh[i], F.GREEDY)[0] for i in range(b)]
+    greedy_ms = (time.perf_counter() - t0) / b * 1e3
+    t0 = time.perf_counter()
+    hung = [F.discretize(Xh[i], F.HUNGARIAN)[0] for i in range(b)]
+    hung_ms = (time.perf_counter() - t0) / b * 1e3
+    return {"device_greedy_ms_per_batch": dev_ms,
+            "device_greedy_ms_per_pair": dev_ms / b,
+            "host_greedy_ms_per_pair": greedy_ms,
+            "host_hungarian_ms_per_pair": hung_ms,
+            "device_equals_host_greedy": bool(all(
+                (got[i] == host[i]).all() for i in range(b))),
+            "greedy_equals_hungarian_pairs": int(sum(
+                (host[i] == hung[i]).all() for i in range(b))),
+            "pairs": b, "n": n}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -353,6 +384,8 @@ def main():
         "autotune": tuned,
     }
     if not args.no_extra:
+        out["discretize"] = discretize_leg(torch, F, S, Xh, X, offs, n,
+                                           args.steps)
         # same workload with BF16 products
         prm16 = F.default_params(lambda_=1.0, team_size=team,
                                  precision=F.BF16, tol_outer=BF16_TOL_OUTER)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FASTPFP_ABI_VERSION 3
+#define FASTPFP_ABI_VERSION 4
 
 typedef struct fastpfp_ctx* fastpfp_t;
 
@@ -212,6 +212,25 @@ fastpfp_status fastpfp_autotune(fastpfp_t h, int N, int batch, int passes,
 fastpfp_status fastpfp_discretize(int n, int np, const float* X_host, int ldx,
                                   int method, int32_t* match_host,
                                   double* score);
+
+/* The greedy rule of FASTPFP_GREEDY (Sec. 4.5) on the device, for a packed
+ * ragged batch of results: pair b's X is n_host[b] x np_host[b], row-major
+ * with row pitch np_host[b], at X + offX_host[b] (device float32, as the
+ * solver leaves it); its matching is written to match + offM_host[b]
+ * (device int32, n_host[b] entries: the column of row i, or -1).  The
+ * matching is identical to fastpfp_discretize(..., FASTPFP_GREEDY, ...):
+ * entries taken by value, ties to the smaller row-major index.  It is found
+ * by parallel row-proposing deferred acceptance on that order, whose unique
+ * stable matching is the greedy one.  Sizes must satisfy
+ * 1 <= n <= max_n, 1 <= n' <= max_np of the handle.  status_host (nullable,
+ * batch entries) receives FASTPFP_OK or FASTPFP_ERR_NUMERIC (X holds a
+ * non-finite entry; that pair's match is all -1); the call returns the first
+ * non-OK pair status.  Grows a handle-owned scratch of about 8 (n'_1 + ... +
+ * n'_batch) bytes; runs on the handle's stream and waits for it. */
+fastpfp_status fastpfp_discretize_greedy_batched(
+    fastpfp_t h, int batch, const int* n_host, const int* np_host,
+    const float* X, const int64_t* offX_host, int32_t* match,
+    const int64_t* offM_host, int* status_host);
 
 /* Copies the eps1 trace (max|X_{t+1} - X_t| per outer step) of the last
  * fastpfp_solve on this handle into out_host (up to cap values); returns the

@@ -26,8 +26,10 @@ ARCH = "gfx950"
 HIP_SOURCES = [("fastpfp_kernels.hip", "fastpfp_kernels", []),
                ("fastpfp_kernels.hip", "fastpfp_kernels_dykstra",
                 ["-DFPFP_DYKSTRA_BUILD=1"]),
-               ("warmstart.hip", "warmstart", [])]
-CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp"]
+               ("warmstart.hip", "warmstart", []),
+               ("discretize_device.hip", "discretize_device", [])]
+CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp",
+               "discretize_device_api.cpp"]
 
 # Packed FP32 VALU instructions stay off: ordinary float code only.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

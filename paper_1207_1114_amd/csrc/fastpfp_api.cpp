@@ -477,6 +477,7 @@ fastpfp_status fastpfp_destroy(fastpfp_t h) {
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->warm) fpfp::warm_free(h->warm);
+  if (h->dws) (void)hipFree(h->dws);
   delete h;
   return FASTPFP_OK;
 }

@@ -27,6 +27,8 @@ struct fastpfp_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> trace;
   fpfp::WarmState* warm = nullptr;
+  void* dws = nullptr;        // device greedy discretisation scratch
+  size_t dws_bytes = 0;
 };
 
 namespace fpfp {

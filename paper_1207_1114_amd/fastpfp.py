@@ -23,7 +23,7 @@ INIT_UNIFORM, INIT_USER = 0, 1
 HUNGARIAN, GREEDY = 0, 1
 ALTERNATING, DYKSTRA = 0, 1
 METHOD_FASTPFP, METHOD_PG = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           3: "HIP runtime error", 4: "out of device memory",
@@ -32,6 +32,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
 
 EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
            "fastpfp_solve", "fastpfp_solve_batched", "fastpfp_project",
+           "fastpfp_discretize_greedy_batched",
            "fastpfp_discretize", "fastpfp_get_trace", "fastpfp_status_string",
            "fastpfp_last_error", "fastpfp_abi_version",
            "fastpfp_warmstart_load", "fastpfp_warmstart_get",
@@ -103,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_warmstart_zero_grad.argtypes = [P]
     lib.fastpfp_warmstart_adam.argtypes = [P, D, D, D, D, D]
     lib.fastpfp_autotune.argtypes = [P, I, I, I, L(I), P, P, I, L(I)]
+    lib.fastpfp_discretize_greedy_batched.argtypes = [P, I, P, P, P, P, P, P,
+                                                      P]
     lib.fastpfp_status_string.argtypes = [I]
     lib.fastpfp_status_string.restype = ctypes.c_char_p
     lib.fastpfp_last_error.argtypes = [P]
@@ -115,7 +118,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "fastpfp_warmstart_features", "fastpfp_warmstart",
                  "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
                  "fastpfp_warmstart_adam", "fastpfp_warmstart_batched",
-                 "fastpfp_autotune"):
+                 "fastpfp_autotune", "fastpfp_discretize_greedy_batched"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.fastpfp_abi_version() != ABI_VERSION:
         raise ImportError(
@@ -257,6 +260,46 @@ class Solver:
             self._raise(st)
         return best.value, list(zip(Ws[:cnt.value].tolist(),
                                      rates[:cnt.value].tolist()))
+
+    def discretize_greedy_batched(self, n: Sequence[int], np_: Sequence[int],
+                                  X, offX, match, offM) -> list:
+        """Device greedy discretisation of a packed batch (X flat float32,
+        match flat int32, both device tensors; offsets in elements).
+        Returns the per-pair statuses; raises on a non-OK call status."""
+        import torch
+        b = len(n)
+        if not (isinstance(match, torch.Tensor) and match.is_cuda
+                and match.dtype == torch.int32):
+            raise TypeError("match must be a device int32 tensor")
+        if not (isinstance(X, torch.Tensor) and X.is_cuda
+                and X.dtype == torch.float32):
+            raise TypeError("X must be a device float32 tensor")
+        ni = np.asarray(n, dtype=np.int32)
+        npi = np.asarray(np_, dtype=np.int32)
+        ox = np.asarray(offX, dtype=np.int64)
+        om = np.asarray(offM, dtype=np.int64)
+        stat = np.zeros(b, dtype=np.int32)
+        c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        st = self._lib.fastpfp_discretize_greedy_batched(
+            self._h, b, c(ni), c(npi), _ptr(X), c(ox), _ptr(match), c(om),
+            c(stat))
+        if st != 0:
+            err = FastPFPError(st, self._lib.fastpfp_last_error(self._h)
+                               .decode(errors="replace"))
+            err.statuses = stat.tolist()
+            raise err
+        return stat.tolist()
+
+    def discretize_greedy(self, X):
+        """Device greedy discretisation of one n x n' device matrix;
+        returns a device int32 tensor of n columns (-1 = unmatched)."""
+        import torch
+        _check_dev(X, "X")
+        Xc = X.contiguous()
+        match = torch.empty(Xc.shape[0], dtype=torch.int32, device=Xc.device)
+        self.discretize_greedy_batched([Xc.shape[0]], [Xc.shape[1]],
+                                       Xc.view(-1), [0], match, [0])
+        return match
 
     # -- learned warm start ------------------------------------------------
 
