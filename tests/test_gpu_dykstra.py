@@ -129,3 +129,60 @@ def test_dykstra_solve_parity_sec51(env, flips, deletion):
                     projection="dykstra")
     assert info["converged"] and ref.converged
     _assert_parity(X, info, ref)
+
+
+@pytest.mark.parametrize("n,m", [(70, 90), (90, 70)])
+def test_dykstra_with_bf16_products_matches_recipe_oracle(env, n, m):
+    """BF16 products with the exact projection against the oracle running
+    the same bfloat16 recipe; one bfloat16 ulp of the largest entry, as for
+    the alternating projection."""
+    torch, F, S = env
+    rng = synth.rng_for(98, n * 1000 + m + 7)
+    A = synth.random_weighted_graph(rng, n, 0.3)
+    B = synth.random_weighted_graph(rng, m, 0.3)
+    K = rng.random((n, m))
+    p = synth.GraphPair(A, B, K, 0.5, np.full(n, -1))
+    kw = dict(max_outer=5, max_inner=120)
+    X, info = _solve(env, p, lambda_=0.5, precision=F.BF16, **kw)
+    ref = O.fastpfp(A, B, K, 0.5, products="bf16", projection="dykstra", **kw)
+    assert np.abs(X - ref.X).max() <= 2.0 ** -8 * np.abs(ref.X).max()
+    assert info["outer_iters"] == ref.outer_iters
+
+
+@pytest.mark.parametrize("method", ["dykstra", "pg"])
+def test_batched_equals_single_for_the_variants(env, method):
+    """A ragged batch with the exact projection or the PG iteration gives
+    every pair bit for bit what a solve of that pair alone gives."""
+    torch, F, S = env
+    pairs = [synth.config3_pair(i) for i in range(4)]
+    pairs += [synth.config3_pair(100, n=50, n_extra=0),
+              synth.config3_pair(101, n=300, n_extra=40)]
+    kw = dict(lambda_=1.0, max_outer=6, max_inner=150, team_size=16)
+    if method == "dykstra":
+        kw["projection"] = F.DYKSTRA
+    else:
+        kw.update(method=F.METHOD_PG, alpha=0.05, normalize_max=0)
+    prm = F.default_params(**kw)
+    offs = {k: [] for k in "ABKX"}
+    bufs = {k: [] for k in "ABKX"}
+    cur = {k: 0 for k in "ABKX"}
+    for p in pairs:
+        for k, mtx in dict(A=p.A, B=p.B, K=p.K,
+                           X=np.zeros((p.n, p.np_))).items():
+            offs[k].append(cur[k])
+            bufs[k].append(np.asarray(mtx, np.float32).ravel())
+            cur[k] += mtx.size
+    d = {k: dev(torch, np.concatenate(v)).view(-1, 1)
+         for k, v in bufs.items()}
+    infos = S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                            d["A"], offs["A"], d["B"], offs["B"], d["K"],
+                            offs["K"], d["X"], offs["X"], prm)
+    Xall = d["X"].cpu().numpy().ravel()
+    for p, o, inf in zip(pairs, offs["X"], infos):
+        Xs = torch.zeros(p.n, p.np_, device="cuda:0")
+        info = S.solve(dev(torch, p.A), dev(torch, p.B), dev(torch, p.K), Xs,
+                       prm)
+        np.testing.assert_array_equal(
+            Xall[o:o + p.n * p.np_].reshape(p.n, p.np_), Xs.cpu().numpy())
+        assert inf["outer_iters"] == info["outer_iters"]
+        assert inf["inner_iters_total"] == info["inner_iters_total"]
