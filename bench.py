@@ -291,6 +291,26 @@ def discretize_leg(torch, F, S, Xh, X, offs, n, steps):
             "pairs": b, "n": n}
 
 
+def projection_leg(torch, F, S, n, team):
+    """Device time per inner pass of the alternating projection (Algorithm 1)
+    and of the exact one (Dykstra) on one n x n matrix, team `team`, 1000
+    passes each from the same seeded input."""
+    rng = np.random.default_rng([1207, 1114, 5, n])
+    Y0 = (rng.normal(size=(n, n)) * 2.0 + 0.5).astype(np.float32)
+    out = {"n": n, "team_size": team, "passes": 1000}
+    for name, proj in (("alternating", F.ALTERNATING),
+                       ("dykstra", F.DYKSTRA)):
+        Y = torch.tensor(Y0, device="cuda:0")
+        S.project(Y, 1e-30, 8, team, projection=proj)      # warm
+        Y = torch.tensor(Y0, device="cuda:0")
+        info = S.project(Y, 1e-30, 1000, team, projection=proj)
+        out[name + "_us_per_pass"] = (info["kernel_ms"] * 1e3
+                                      / max(1, info["inner_iters_total"]))
+    out["dykstra_over_alternating"] = (out["dykstra_us_per_pass"]
+                                       / out["alternating_us_per_pass"])
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -386,6 +406,7 @@ def main():
     if not args.no_extra:
         out["discretize"] = discretize_leg(torch, F, S, Xh, X, offs, n,
                                            args.steps)
+        out["projection"] = projection_leg(torch, F, S, n, team)
         # same workload with BF16 products
         prm16 = F.default_params(lambda_=1.0, team_size=team,
                                  precision=F.BF16, tol_outer=BF16_TOL_OUTER)
