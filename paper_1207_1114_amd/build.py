@@ -49,20 +49,26 @@ def _run(cmd: list[str]) -> None:
         print(out, file=sys.stderr)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Compiles every source (independent compiles in parallel) and links
+    the library; always rebuilds."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
-    objs = []
+    cmds, objs = [], []
     for src, name, defs in HIP_SOURCES:
         obj = os.path.join(BUILD, name + ".hip.o")
-        _run([hipcc, *HIPCC_FLAGS, *defs, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
-              os.path.join(CSRC, src), "-o", obj])
+        cmds.append([hipcc, *HIPCC_FLAGS, *defs, f"-I{INCLUDE}", f"-I{CSRC}",
+                     "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", *CXX_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
-              os.path.join(CSRC, src), "-o", obj])
+        cmds.append(["g++", *CXX_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
+                     os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as pool:
+        for f in [pool.submit(_run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o",
           tmp])
