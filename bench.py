@@ -190,6 +190,7 @@ def traffic_bytes(args, team):
 
 
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense
+HBM_PEAK_GBS = 8000.0                                 # MI355X HBM3E
 
 
 def products_leg(torch, F, S, ns, nps, A, B, K, X, offs, team, steps):
@@ -311,6 +312,28 @@ def projection_leg(torch, F, S, n, team):
     return out
 
 
+def stream_leg(torch, F, sizes=(8192, 16384), passes=50):
+    """Steps 4-7 with Y in HBM (fastpfp_project_stream) on random nonnegative
+    N x N matrices too large for the on-chip path: 8 N^2 algorithmic bytes
+    per pass (read Y, write D) against the 8 TB/s HBM peak.  The time is the
+    whole call (launches, and a flag check every 32 passes, included)."""
+    out = {"passes": passes, "bytes_per_pass": "8 N^2"}
+    S = F.Solver(max(sizes), max(sizes))
+    g = torch.Generator(device="cuda:0")
+    for N in sizes:
+        g.manual_seed(N)
+        Y = torch.rand(N, N, device="cuda:0", generator=g)
+        S.project_stream(Y, 1e-30, 2)                      # warm
+        info = S.project_stream(Y, 1e-30, passes)
+        us = info["kernel_ms"] * 1e3 / info["inner_iters_total"]
+        gbs = 8.0 * N * N / (us * 1e-6) / 1e9
+        out[str(N)] = {"us_per_pass": us, "GB_per_s": gbs,
+                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+        del Y
+    S.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -407,6 +430,7 @@ def main():
         out["discretize"] = discretize_leg(torch, F, S, Xh, X, offs, n,
                                            args.steps)
         out["projection"] = projection_leg(torch, F, S, n, team)
+        out["projection_stream"] = stream_leg(torch, F)
         # same workload with BF16 products
         prm16 = F.default_params(lambda_=1.0, team_size=team,
                                  precision=F.BF16, tol_outer=BF16_TOL_OUTER)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FASTPFP_ABI_VERSION 4
+#define FASTPFP_ABI_VERSION 5
 
 typedef struct fastpfp_ctx* fastpfp_t;
 
@@ -185,6 +185,20 @@ fastpfp_status fastpfp_solve_batched(fastpfp_t h, int batch,
 fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
                                int max_inner, int team_size, int projection,
                                fastpfp_info* info);
+
+/* The same inner repeat with Y kept in device memory instead of on chip:
+ * every pass reads and writes the N x N matrix once (8 N^2 bytes), so it is
+ * bound by HBM bandwidth and has no size limit beyond the handle's
+ * (N <= max(max_n, max_np)) and memory.  fastpfp_project takes this path by
+ * itself for N > 4096 with team_size = 0.  Same arithmetic per entry as the
+ * on-chip path (row and column sums reduced in another fixed order; s in
+ * float64), same stopping rule and pass count; info->kernel_ms covers the
+ * whole call.  Y (device, row pitch N) must hold N x N floats.  Grows a
+ * handle-owned scratch of about 4 N (N/64 + N/1024 + 3) bytes.  Returns
+ * FASTPFP_ERR_NUMERIC if a sum or max|dY| turns non-finite. */
+fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y, double tol,
+                                      int max_inner, int projection,
+                                      fastpfp_info* info);
 
 /* Team-size autotuner.  A pair is solved by a team of W workgroups cut
  * into a TR x TC grid of tiles; larger teams finish one pair faster but

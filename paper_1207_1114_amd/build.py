@@ -27,9 +27,10 @@ HIP_SOURCES = [("fastpfp_kernels.hip", "fastpfp_kernels", []),
                ("fastpfp_kernels.hip", "fastpfp_kernels_dykstra",
                 ["-DFPFP_DYKSTRA_BUILD=1"]),
                ("warmstart.hip", "warmstart", []),
-               ("discretize_device.hip", "discretize_device", [])]
+               ("discretize_device.hip", "discretize_device", []),
+               ("project_stream.hip", "project_stream", [])]
 CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp",
-               "discretize_device_api.cpp"]
+               "discretize_device_api.cpp", "project_stream_api.cpp"]
 
 # Packed FP32 VALU instructions stay off: ordinary float code only.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -478,6 +478,7 @@ fastpfp_status fastpfp_destroy(fastpfp_t h) {
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   if (h->warm) fpfp::warm_free(h->warm);
   if (h->dws) (void)hipFree(h->dws);
+  if (h->pws) (void)hipFree(h->pws);
   delete h;
   return FASTPFP_OK;
 }
@@ -568,6 +569,10 @@ fastpfp_status fastpfp_project(fastpfp_t h, int N, float* Y, double tol,
       projection != FASTPFP_PROJ_DYKSTRA)
     return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown projection %d",
                 projection);
+  // a matrix no team can hold on chip is projected with Y in HBM
+  Plan pl;
+  if (team_size == 0 && !plan_team(N, 0, &pl))
+    return fastpfp_project_stream(h, N, Y, tol, max_inner, projection, info);
   std::vector<PairIn> pairs(1);
   pairs[0] = PairIn{N, N, nullptr, nullptr, nullptr, nullptr, Y, N, N, N, N};
   fastpfp_info tmp;

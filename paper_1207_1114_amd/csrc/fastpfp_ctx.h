@@ -29,6 +29,8 @@ struct fastpfp_ctx {
   fpfp::WarmState* warm = nullptr;
   void* dws = nullptr;        // device greedy discretisation scratch
   size_t dws_bytes = 0;
+  void* pws = nullptr;        // streaming projection scratch
+  size_t pws_bytes = 0;
 };
 
 namespace fpfp {

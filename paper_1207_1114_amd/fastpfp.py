@@ -23,7 +23,7 @@ INIT_UNIFORM, INIT_USER = 0, 1
 HUNGARIAN, GREEDY = 0, 1
 ALTERNATING, DYKSTRA = 0, 1
 METHOD_FASTPFP, METHOD_PG = 0, 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           3: "HIP runtime error", 4: "out of device memory",
@@ -32,7 +32,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
 
 EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
            "fastpfp_solve", "fastpfp_solve_batched", "fastpfp_project",
-           "fastpfp_discretize_greedy_batched",
+           "fastpfp_discretize_greedy_batched", "fastpfp_project_stream",
            "fastpfp_discretize", "fastpfp_get_trace", "fastpfp_status_string",
            "fastpfp_last_error", "fastpfp_abi_version",
            "fastpfp_warmstart_load", "fastpfp_warmstart_get",
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_autotune.argtypes = [P, I, I, I, L(I), P, P, I, L(I)]
     lib.fastpfp_discretize_greedy_batched.argtypes = [P, I, P, P, P, P, P, P,
                                                       P]
+    lib.fastpfp_project_stream.argtypes = [P, I, P, ctypes.c_double, I, I,
+                                           L(Info)]
     lib.fastpfp_status_string.argtypes = [I]
     lib.fastpfp_status_string.restype = ctypes.c_char_p
     lib.fastpfp_last_error.argtypes = [P]
@@ -118,7 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                  "fastpfp_warmstart_features", "fastpfp_warmstart",
                  "fastpfp_warmstart_grad", "fastpfp_warmstart_zero_grad",
                  "fastpfp_warmstart_adam", "fastpfp_warmstart_batched",
-                 "fastpfp_autotune", "fastpfp_discretize_greedy_batched"):
+                 "fastpfp_autotune", "fastpfp_discretize_greedy_batched",
+                 "fastpfp_project_stream"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.fastpfp_abi_version() != ABI_VERSION:
         raise ImportError(
@@ -238,10 +241,26 @@ class Solver:
     def project(self, Y, tol: float, max_inner: int, team_size: int = 0,
                 projection: int = ALTERNATING) -> dict:
         _check_dev(Y, "Y")
+        if Y.shape[0] != Y.shape[1] or not Y.is_contiguous():
+            raise ValueError("Y must be a contiguous square matrix")
         info = Info()
         st = self._lib.fastpfp_project(self._h, Y.shape[0], _ptr(Y), tol,
                                        max_inner, team_size, projection,
                                        ctypes.byref(info))
+        if st != 0:
+            self._raise(st)
+        return info.as_dict()
+
+    def project_stream(self, Y, tol: float, max_inner: int,
+                       projection: int = ALTERNATING) -> dict:
+        """Steps 4-7 with Y kept in device memory (any N; HBM-bound)."""
+        _check_dev(Y, "Y")
+        if Y.shape[0] != Y.shape[1] or not Y.is_contiguous():
+            raise ValueError("Y must be a contiguous square matrix")
+        info = Info()
+        st = self._lib.fastpfp_project_stream(self._h, Y.shape[0], _ptr(Y),
+                                              tol, max_inner, projection,
+                                              ctypes.byref(info))
         if st != 0:
             self._raise(st)
         return info.as_dict()

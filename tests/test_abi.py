@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(F):
     for nm in names:
         assert hasattr(lib, nm), nm
     assert set(F.EXPORTS) <= set(names)
-    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 4
+    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 5
 
 
 def test_status_strings_and_defaults(F):
@@ -56,6 +56,8 @@ def test_null_handle_is_rejected_before_any_device_call(F):
     assert lib.fastpfp_project(None, 4, None, 1e-6, 10, 0, 0,
                                ctypes.byref(info)) == 1
     assert lib.fastpfp_destroy(None) == 1
+    assert lib.fastpfp_project_stream(None, 4, None, 1e-6, 10, 0,
+                                      ctypes.byref(info)) == 1
     assert lib.fastpfp_discretize_greedy_batched(None, 1, None, None, None,
                                                  None, None, None,
                                                  None) == 1

@@ -53,8 +53,10 @@ def test_dykstra_projection_parity(env, N, T, team):
     # both stop early only on an exact fixed point (max|dY| = 0 < 1e-30),
     # which float32 rounding may reach a pass before or after float64
     it = info["inner_iters_total"]
-    assert it == ref.iters or (info["eps2_last"] == 0.0 and ref.converged
-                               and abs(it - ref.iters) <= 2)
+    # an early stop is only allowed on an exact float32 fixed point
+    # (max|dY| = 0), which float64 may reach a little later or not at all
+    assert it == ref.iters or (info["eps2_last"] == 0.0 and (
+        it < ref.iters or (ref.converged and it - ref.iters <= 2)))
 
 
 def _certificate(Y, D):

@@ -194,8 +194,10 @@ def test_invalid_arguments_are_rejected(env):
         gpu_solve(env, p, lambda_=1.0)
     assert e.value.status == 1
     with pytest.raises(F.FastPFPError) as e:    # beyond the handle bound
-        S.project(dev(torch, np.zeros((4097, 1))), 1e-6, 3)
+        S.project(torch.zeros(4097, 4097, device="cuda:0"), 1e-6, 3)
     assert e.value.status == 2
+    with pytest.raises(ValueError):              # Y must be square
+        S.project(dev(torch, np.zeros((8, 3))), 1e-6, 3)
 
 
 # ---------------------------------------------------------------- batches
