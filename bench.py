@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=4000,
                     help="inner passes of the oracle timed for the baseline")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="run only the streaming-projection leg (N = 8192, "
+                         "16384) and an in-place elementwise add on the same "
+                         "matrices for reference, print one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for "
                          "HBM byte counters) and exit")
@@ -334,6 +338,28 @@ def stream_leg(torch, F, sizes=(8192, 16384), passes=50):
     return out
 
 
+def elementwise_reference(torch, sizes=(8192, 16384), reps=20):
+    """In-place Y += 1 on the same N x N float32 matrices (8 N^2 bytes per
+    call, like a projection pass): what a plain streaming kernel reaches."""
+    out = {}
+    for N in sizes:
+        Y = torch.rand(N, N, device="cuda:0")
+        for _ in range(3):
+            Y.add_(1.0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            Y.add_(1.0)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out[str(N)] = {"us": us, "GB_per_s": 8.0 * N * N / (us * 1e-6) / 1e9}
+        del Y
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -342,6 +368,12 @@ def main():
               "not built.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.stream_only:
+        from paper_1207_1114_amd import fastpfp as F
+        print(json.dumps({"projection_stream": stream_leg(torch, F),
+                          "elementwise_add_reference":
+                              elementwise_reference(torch)}), flush=True)
+        return
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         y = torch.empty_like(x)
@@ -431,6 +463,8 @@ def main():
                                            args.steps)
         out["projection"] = projection_leg(torch, F, S, n, team)
         out["projection_stream"] = stream_leg(torch, F)
+        out["projection_stream"]["elementwise_add_reference"] = \
+            elementwise_reference(torch)
         # same workload with BF16 products
         prm16 = F.default_params(lambda_=1.0, team_size=team,
                                  precision=F.BF16, tol_outer=BF16_TOL_OUTER)
