@@ -2,15 +2,16 @@
 // matrix that does not fit on chip: Y stays in HBM and every pass reads and
 // writes it once (8 N^2 bytes), so the pass is bound by HBM bandwidth.
 //
-// One pass is two launches on the caller's stream:
+// One pass is three launches on the caller's stream (the kernel boundaries
+// make each one's results visible to the next without fences):
 //   stream_pass   tiles of kSR x kSC entries: D = max(0, Y + a_i + b_j)
 //                 written in place, with per-tile row partials, column
 //                 partials and the tile's max|D - Y|;
 //   stream_reduce r_i and c_j from the partials in a fixed order, giving
-//                 (1 - r_i)/N (float64) and b_j = (1 - c_j)/N, and, in the
-//                 last workgroup to finish, s = 1^T D 1 (float64, fixed
-//                 order), max|dY|, the stop test (max|dY| < eps2) and the
-//                 pass count.
+//                 (1 - r_i)/N (float64) and b_j = (1 - c_j)/N, and partials
+//                 of s;
+//   stream_final  s = 1^T D 1 (float64, fixed order), max|dY|, the stop test
+//                 (max|dY| < eps2) and the pass count.
 // After the stop test holds, later launches of the same call return at once,
 // so the host can enqueue passes in chunks and check the flag in between.
 // a_i = (1 - r_i)/N + (s - N)/N^2 is formed from the float64 parts as the
@@ -30,8 +31,6 @@ constexpr int kSC = 1024;          // columns per tile: 4 waves x 256
 constexpr int kSThreads = 256;
 constexpr int kRC = 16;            // reduction: columns (and rows) per workgroup
 constexpr int kRQ = 16;            // reduction: partial chunks per column
-constexpr int kTG = 32;            // ticket groups (one counter each)
-constexpr int kTStride = 32;       // unsigneds between counters (128 bytes)
 
 // Wave sum with DPP moves (register to register, no LDS): four steps sum
 // each 16-lane row, two row broadcasts carry the row sums up to lane 63.
@@ -194,20 +193,13 @@ stream_pass(StreamState st, int first) {
 // Workgroup b reduces columns and rows b*kRC .. b*kRC + kRC - 1: thread t
 // sums chunk q = t / kRC of the partials of column / row b*kRC + t % kRC
 // (every kRQ-th tile row / column), then the kRQ chunk sums are added in a
-// fixed order.  It writes (1 - r_i)/N (float64) and b_j = (1 - c_j)/N and a
-// float64 partial of s over its rows.  The last workgroup to finish (ticket)
-// adds the partials in block order into s, takes max|dY| over the tiles,
-// applies the stop test, counts the pass and resets the ticket.
-//   ctl: 0 running, 1 converged, 2 non-finite values.
-//   scal[0] = s, scal[1] = last max|dY|; counters[0] = passes done.
+// fixed order.  It writes (1 - r_i)/N (float64), b_j = (1 - c_j)/N and a
+// float64 partial of s over its rows.
 __global__ void __launch_bounds__(kSThreads)
-stream_reduce(StreamState st, int TR, int TC, int is_pass, double tol) {
+stream_reduce(StreamState st, int TR, int TC) {
   if (__hip_atomic_load(st.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     return;
   __shared__ float lc[kRQ][kRC], lr[kRQ][kRC];
-  __shared__ double ld[4];
-  __shared__ float lm[4];
-  __shared__ unsigned last;
   const long long N = st.N;
   const int t = threadIdx.x, q = t / kRC, e = t % kRC;
   const int lane = t & 63, wave = t >> 6;
@@ -241,33 +233,27 @@ stream_reduce(StreamState st, int TR, int TC, int is_pass, double tol) {
     const double w = wave_sum_dd(rpart);
     if (lane == 0) st.spart[blockIdx.x] = w;
   }
-  __syncthreads();
-  if (t == 0) {
-    // two-level ticket: blocks of group b % kTG count on their group's
-    // counter, the last of each group on the main one
-    const unsigned G = gridDim.x, grp = blockIdx.x % kTG;
-    const unsigned gsize = (G - grp + kTG - 1) / kTG;
-    const unsigned ngroups = G < (unsigned)kTG ? G : (unsigned)kTG;
-    unsigned* gc = st.ticket + (1 + grp) * kTStride;
-    last = 0u;
-    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL,
-                               __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
-      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (__hip_atomic_fetch_add(st.ticket, 1u, __ATOMIC_ACQ_REL,
-                                 __HIP_MEMORY_SCOPE_AGENT) == ngroups - 1)
-        last = 1u;
-    }
-  }
-  __syncthreads();
-  if (!last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// One workgroup, after stream_reduce: s from the partials in block order,
+// max|dY| over the tiles, the stop test and the pass count.
+//   ctl: 0 running, 1 converged, 2 non-finite values.
+//   scal[0] = s, scal[1] = last max|dY|; counters[0] = passes done.
+__global__ void __launch_bounds__(kSThreads)
+stream_final(StreamState st, int nparts, int ntiles, int is_pass,
+             double tol) {
+  if (__hip_atomic_load(st.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+    return;
+  __shared__ double ld[4];
+  __shared__ float lm[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   // unrolled so that the independent loads are in flight together
   double sp = 0.0;
 #pragma unroll 8
-  for (unsigned k = t; k < gridDim.x; k += kSThreads) sp += st.spart[k];
+  for (int k = t; k < nparts; k += kSThreads) sp += st.spart[k];
   float m = 0.f;
 #pragma unroll 8
-  for (int k = t; k < TR * TC; k += kSThreads) m = fmaxf(m, st.tmax[k]);
+  for (int k = t; k < ntiles; k += kSThreads) m = fmaxf(m, st.tmax[k]);
   sp = wave_sum_dd(sp);
   m = wave_max_f(m);
   if (lane == 0) {
@@ -287,8 +273,6 @@ stream_reduce(StreamState st, int TR, int TC, int is_pass, double tol) {
       st.counters[0] += 1u;
       if (M < tol) ctl = 1u;
     }
-    __hip_atomic_store(st.ticket, 0u, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
     if (ctl != 0u)
       __hip_atomic_store(st.ctl, ctl, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
@@ -325,8 +309,11 @@ extern "C" hipError_t fpfp_stream_step(const fpfp::StreamState* st, int mode,
 #undef FPFP_PASS
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  fpfp::stream_reduce<<<dim3((unsigned)((st->N + fpfp::kRC - 1) /
-                                        fpfp::kRC)),
-                        block, 0, stream>>>(*st, TR, TC, mode != 0, tol);
+  const unsigned nrb = (unsigned)((st->N + fpfp::kRC - 1) / fpfp::kRC);
+  fpfp::stream_reduce<<<dim3(nrb), block, 0, stream>>>(*st, TR, TC);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  fpfp::stream_final<<<dim3(1), block, 0, stream>>>(*st, (int)nrb, TR * TC,
+                                                    mode != 0, tol);
   return hipGetLastError();
 }

@@ -48,7 +48,6 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
   const size_t o_sp = off; off = align256(off + sizeof(double) * nrb);
   const size_t o_sc = off; off = align256(off + sizeof(double) * 2);
   const size_t o_ct = off; off = align256(off + sizeof(unsigned) * 2);
-  const size_t o_tk = off; off = align256(off + sizeof(unsigned) * 33 * 32);
   const size_t need = off;
   if (need > h->pws_bytes) {
     if (h->pws) (void)hipFree(h->pws);
@@ -74,12 +73,9 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
   unsigned* cw = (unsigned*)(base + o_ct);
   st.ctl = cw;
   st.counters = cw + 1;
-  st.ticket = (unsigned*)(base + o_tk);
   const bool dyk = projection == FASTPFP_PROJ_DYKSTRA;
   HIPCHK(h, hipMemsetAsync(base + o_sc, 0, sizeof(double) * 2, h->stream));
   HIPCHK(h, hipMemsetAsync(cw, 0, sizeof(unsigned) * 2, h->stream));
-  HIPCHK(h, hipMemsetAsync(st.ticket, 0, sizeof(unsigned) * 33 * 32,
-                           h->stream));
   HIPCHK(h, hipEventRecord(h->ev0, h->stream));
   HIPCHK(h, fpfp_stream_step(&st, 0, 0, tol, h->stream));
   // passes go out in chunks; once the stop test holds (or values turn

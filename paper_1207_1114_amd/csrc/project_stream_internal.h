@@ -14,8 +14,6 @@ struct StreamState {
   float* colpart;       // [TR][N] column partials of each tile row
   float* tmax;          // [TR * TC] tile max|dY|
   double* spart;        // [ceil(N / 16)] partials of s, one per reduce block
-  unsigned* ticket;     // [0] groups finished, [32 (1 + g)] blocks of group
-                        // g finished, in this pass (33 x 128 bytes)
   double* scal;         // [0] s = 1^T Y 1, [1] last max|dY|
   unsigned* counters;   // [0] passes run
   unsigned* ctl;        // 0 running, 1 converged, 2 non-finite
