@@ -904,18 +904,32 @@ fastpfp_persistent(LaunchDesc L) {
         // tile's storage
         const float alpha = pd.alpha, beta = 1.f - pd.alpha;
         float mloc = 0.f;
+        // X of tile row a + 1 is loaded while row a is updated, so each
+        // row's loads are in flight behind the previous row's arithmetic
         {
           const int rmax = opaque(rmax_), cmax = opaque(cmax_);
+          float xa[kCB], xb[kCB];
+          auto load_xrow = [&](int a, float (&dst)[kCB]) {
+            const int li = pr + 16 * a;
+            const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+#pragma unroll
+            for (int bb = 0; bb < kCB; ++bb)
+              dst[bb] = (li < rmax && pc + 16 * bb < cmax) ? xrow[16 * bb]
+                                                           : 0.f;
+          };
+          load_xrow(0, xa);
 #pragma unroll
           for (int a = 0; a < kRA; ++a) {
+            float(&cur)[kCB] = (a & 1) ? xb : xa;
+            float(&nxt)[kCB] = (a & 1) ? xa : xb;
+            if (a + 1 < kRA) load_xrow(a + 1, nxt);
             const int li = pr + 16 * a;
             if (li < rmax) {
-              const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
 #pragma unroll
               for (int bb = 0; bb < kCB; ++bb)
                 if (pc + 16 * bb < cmax) {
                   const float y = (a < kRegRows) ? Yr[a][bb] : FPFP_LY(a, bb);
-                  const float xn = beta * xrow[16 * bb] + alpha * y;
+                  const float xn = beta * cur[bb] + alpha * y;
                   if (a < kRegRows) Yr[a][bb] = xn;
                   else FPFP_LY(a, bb) = xn;
                   mloc = fmaxf(mloc, xn);
@@ -937,6 +951,39 @@ fastpfp_persistent(LaunchDesc L) {
         }
         const bool norm = pd.normalize;
         float eloc = 0.f;
+        // eps1 = max|X_new / m - X| first, reading the previous X with the
+        // same one-row lookahead as step 8; then X = X_new / m is written by
+        // a store-only sweep, which has no loads to wait on
+        {
+          const int rmax = opaque(rmax_), cmax = opaque(cmax_);
+          float xa[kCB], xb[kCB];
+          auto load_xrow = [&](int a, float (&dst)[kCB]) {
+            const int li = pr + 16 * a;
+            const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+#pragma unroll
+            for (int bb = 0; bb < kCB; ++bb)
+              dst[bb] = (li < rmax && pc + 16 * bb < cmax) ? xrow[16 * bb]
+                                                           : 0.f;
+          };
+          load_xrow(0, xa);
+#pragma unroll
+          for (int a = 0; a < kRA; ++a) {
+            float(&cur)[kCB] = (a & 1) ? xb : xa;
+            float(&nxt)[kCB] = (a & 1) ? xa : xb;
+            if (a + 1 < kRA) load_xrow(a + 1, nxt);
+            const int li = pr + 16 * a;
+            if (li < rmax) {
+#pragma unroll
+              for (int bb = 0; bb < kCB; ++bb)
+                if (pc + 16 * bb < cmax) {
+                  const float xn = (a < kRegRows) ? Yr[a][bb] : FPFP_LY(a, bb);
+                  const float xv = norm ? xn / m : xn;
+                  eloc = fmaxf(eloc, fabsf(xv - cur[bb]));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
         {
           const int rmax = opaque(rmax_), cmax = opaque(cmax_);
 #pragma unroll
@@ -949,7 +996,6 @@ fastpfp_persistent(LaunchDesc L) {
                 if (pc + 16 * bb < cmax) {
                   const float xn = (a < kRegRows) ? Yr[a][bb] : FPFP_LY(a, bb);
                   const float xv = norm ? xn / m : xn;
-                  eloc = fmaxf(eloc, fabsf(xv - xrow[16 * bb]));
                   xrow[16 * bb] = xv;
                   if (bf)
                     Xh[(long long)(g.c0 + pc + 16 * bb) * Np + g.r0 + li] =
