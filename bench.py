@@ -363,9 +363,9 @@ def elementwise_reference(torch, sizes=(8192, 16384), reps=20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the "
-              "multi-GPU sharding of this path is described in DESIGN.md but "
-              "not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); "
+              "sharding pairs over several GPUs is not built.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if args.stream_only:

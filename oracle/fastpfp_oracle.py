@@ -35,7 +35,7 @@ matrix products as the only library primitive:
 * ``objective``           eq. (3): 1/2 tr(P^T A P A') + lambda tr(P^T K).
 * ``matching_error``      eq. (1): 1/2 ||A - P A' P^T||^2 + lambda ||F - P G||^2.
 
-Readings taken where the paper is loose (each one also listed in the design doc):
+Readings taken where the paper is loose:
 
 * Orientation.  The paper assumes n >= n' (columns of X sum to one, rows to
   at most one).  Both orientations are handled natively: Y is N x N with

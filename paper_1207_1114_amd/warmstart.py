@@ -1,5 +1,5 @@
 """Learned warm start: training it on fixed points of the plain method, and
-solving with it while the uniform start stays the fallback and the judge.
+solving with it while the uniform start stays the fallback and the reference.
 
 The network and its kernels live in the library (``fastpfp_warmstart*``
 entry points); this module only orchestrates them.
@@ -309,7 +309,7 @@ def warm_params():
 
 
 def run_plain(S, torch, b: Batch, prm=None, repeats: int = 1) -> dict:
-    """The judge: FP32 products from the uniform start."""
+    """The reference run: FP32 products from the uniform start."""
     prm = prm or F.default_params(lambda_=1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -2,9 +2,9 @@
 
 Held-out pairs of the config-4 model (evaluation seeds 100-107, outside the
 pairs the acceptance check used) at n = 1000 are solved three ways: the
-plain method (FP32 products, uniform start, eps1 = 1e-6) -- the judge; BF16
+plain method (FP32 products, uniform start, eps1 = 1e-6) -- the reference; BF16
 products from the uniform start; and BF16 products from the shipped learned
-start (both with the BF16 eps1).  The learned start must match the judge's
+start (both with the BF16 eps1).  The learned start must match the reference's
 objective (1e-3 relative) and accuracy (0.5 pp) with at most 0.6 of its
 outer steps (about half were measured), and take fewer outer steps than the uniform start at the same
 precision, which isolates what the network itself contributes.
@@ -45,7 +45,7 @@ def test_learned_start_beats_the_uniform_start_at_the_same_precision(runs):
     assert warm.get("fallbacks", 0) == 0
 
 
-def test_learned_start_matches_the_plain_fp32_judge(runs):
+def test_learned_start_matches_the_plain_fp32_reference(runs):
     W, r = runs
     v = W.verdict(r["plain_fp32"], r["warm_bf16"])
     assert v["accepted"], v
