@@ -104,3 +104,18 @@ def test_pg_argument_checks(env):
                {"method": F.METHOD_PG, "alpha": float("inf")}):
         with pytest.raises(F.FastPFPError):
             S.solve(A, A, None, X, F.default_params(max_outer=2, **kw))
+
+
+def test_pg_with_bf16_products_matches_recipe_oracle(env):
+    """PG with BF16 products against the oracle running the same bfloat16
+    recipe: one bfloat16 ulp of the largest entry, as for FastPFP."""
+    torch, F, S = env
+    rng = synth.rng_for(98, 70 * 1000 + 90 + 11)
+    A = synth.random_weighted_graph(rng, 70, 0.3)
+    B = synth.random_weighted_graph(rng, 90, 0.3)
+    K = rng.random((70, 90))
+    kw = dict(max_outer=5, max_inner=120)
+    X, info = _solve(env, A, B, K, 0.5, alpha=0.1, precision=F.BF16, **kw)
+    ref = O.projected_gradient(A, B, K, 0.5, 0.1, products="bf16", **kw)
+    assert np.abs(X - ref.X).max() <= 2.0 ** -8 * np.abs(ref.X).max()
+    assert info["outer_iters"] == ref.outer_iters

@@ -82,3 +82,14 @@ def test_stream_non_finite_input(env):
     with pytest.raises(F.FastPFPError) as e:
         S.project_stream(dev(torch, Y), 1e-6, 10)
     assert e.value.status == 5
+
+
+def test_large_n_exact_projection_routes_to_the_stream(env):
+    torch, F, S = env
+    N, T = 4100, 3
+    rng = np.random.default_rng(17)
+    Y = (rng.random((N, N)) * 2.0 - 0.5).astype(np.float32)
+    Yg = dev(torch, Y)
+    info = S.project(Yg, 1e-30, T, projection=F.DYKSTRA)
+    _cmp(info, Yg.cpu().numpy(), O.dykstra_inner(Y.astype(np.float64),
+                                                 1e-30, T))
