@@ -9,7 +9,7 @@
 #include "fastpfp_ctx.h"
 #include "project_stream_internal.h"
 
-extern "C" void fpfp_stream_tiles(long long N, int* TR, int* TC);
+extern "C" void fpfp_stream_geometry(long long N, int* TR, int* TC, int* nrb);
 extern "C" hipError_t fpfp_stream_step(const fpfp::StreamState* st, int mode,
                                        int first, double tol,
                                        hipStream_t stream);
@@ -35,15 +35,15 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
     return fail(h, FASTPFP_ERR_INVALID_ARG, "unknown projection %d",
                 projection);
   HIPCHK(h, hipSetDevice(h->device));
-  int TR = 0, TC = 0;
-  fpfp_stream_tiles(N, &TR, &TC);
+  int TR = 0, TC = 0, nrb_i = 0;
+  fpfp_stream_geometry(N, &TR, &TC, &nrb_i);
   const size_t nt = (size_t)TR * TC;
   size_t off = 0;
   const size_t o_a = off;  off = align256(off + sizeof(double) * N);
   const size_t o_b = off;  off = align256(off + sizeof(float) * N);
   const size_t o_rp = off; off = align256(off + sizeof(float) * N * (size_t)TC);
   const size_t o_cp = off; off = align256(off + sizeof(float) * N * (size_t)TR);
-  const size_t nrb = ((size_t)N + 15) / 16;  // reduce blocks
+  const size_t nrb = (size_t)nrb_i;  // reduce blocks
   const size_t o_tm = off; off = align256(off + sizeof(float) * nt);
   const size_t o_sp = off; off = align256(off + sizeof(double) * nrb);
   const size_t o_sc = off; off = align256(off + sizeof(double) * 2);
