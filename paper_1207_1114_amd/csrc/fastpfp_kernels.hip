@@ -653,9 +653,17 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
   d = 0.f;
   if (!*numeric) {
     for (u = 1; u <= max_inner; ++u) {
-      float bv[kCB];
+      // LDS reads are issued well ahead of their use (one wave per SIMD has
+      // nothing else to cover their latency): b of P1 first, a of P1 one row
+      // ahead, the first LDS-resident row while the register rows are
+      // updated, and each entry of a further LDS row as soon as the entry
+      // above it has been updated
+      float bv[kCB], yl[kCB];
 #pragma unroll
       for (int b = 0; b < kCB; ++b) bv[b] = sh.b_l[pc + 16 * b];
+      float av_next = sh.a_l[pr];
+#pragma unroll
+      for (int b = 0; b < kCB; ++b) yl[b] = FPFP_LY(kRegRows, b);
       float dm = 0.f;
       // Dykstra: floor of the previous iterate max(w, lo); the first pass
       // compares with the unclamped input
@@ -664,26 +672,33 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
       for (int b = 0; b < kCB; ++b) cs[b] = 0.f;
 #pragma unroll
       for (int a = 0; a < kRA; ++a) {
-        const float av = sh.a_l[pr + 16 * a];
+        const float av_a = av_next;
+        if (a + 1 < kRA) av_next = sh.a_l[pr + 16 * (a + 1)];
         float r = 0.f;
 #pragma unroll
         for (int b = 0; b < kCB; ++b) {
-          const float y = (a < kRegRows) ? Yr[a][b] : FPFP_LY(a, b);
+          const float y = (a < kRegRows) ? Yr[a][b] : yl[b];
           float dd;
           if constexpr (kDyk) {
-            dd = (y + av) + bv[b];
+            dd = (y + av_a) + bv[b];
             const float xn = fmaxf(dd, 0.f);
             dm = fmaxf(dm, fabsf(xn - fmaxf(y, lo)));
             r += xn;
             cs[b] += xn;
           } else {
-            dd = fmaxf((y + av) + bv[b], 0.f);
+            dd = fmaxf((y + av_a) + bv[b], 0.f);
             dm = fmaxf(dm, fabsf(dd - y));
             r += dd;
             cs[b] += dd;
           }
-          if (a < kRegRows) Yr[a][b] = dd;
-          else FPFP_LY(a, b) = dd;
+          if (a < kRegRows) {
+            Yr[a][b] = dd;
+          } else {
+            FPFP_LY(a, b) = dd;
+            // the register just used takes the same column of the next LDS
+            // row, which then has the rest of this row to arrive
+            if (a + 1 < kRA) yl[b] = FPFP_LY(a + 1, b);
+          }
         }
         rs[a] = r;
       }
