@@ -266,17 +266,21 @@ stream_pass(StreamState st, int first) {
 // lane: wave q sums the partials of tile rows (tile columns) q, q + kRQ,
 // ..., so each load of a wave reads kRC consecutive floats; the kRQ wave
 // sums are then added in wave order.  It writes (1 - r_i)/N (float64),
-// b_j = (1 - c_j)/N and a float64 partial of s over its rows.
+// b_j = (1 - c_j)/N and a float64 partial of s over its rows.  Since
+// kRC = kSR, workgroup b also takes the max|dY| of tile row b.
 __global__ void __launch_bounds__(kRThreads)
 stream_reduce(StreamState st, int TR, int TC) {
   if (__hip_atomic_load(st.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     return;
   static_assert(kRC == 64 && kRQ * 64 == kRThreads, "a lane per column");
-  __shared__ float lc[kRQ][kRC], lr[kRQ][kRC];
+  static_assert(kRC == kSR, "one reduce workgroup per tile row");
+  __shared__ float lc[kRQ][kRC], lr[kRQ][kRC], lm[kRQ];
   const long long N = st.N;
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const long long g = (long long)blockIdx.x * kRC + lane;
-  float c = 0.f, r = 0.f;
+  float c = 0.f, r = 0.f, m = 0.f;
+  for (int k = threadIdx.x; k < TC; k += kRThreads)
+    m = fmaxf(m, st.tmax[(long long)blockIdx.x * TC + k]);
   if (g < N) {
     // unrolled so that the independent loads are in flight together
 #pragma unroll 8
@@ -286,8 +290,16 @@ stream_reduce(StreamState st, int TR, int TC) {
   }
   lc[q][lane] = c;
   lr[q][lane] = r;
+  m = wave_max_f(m);
+  if (lane == 0) lm[q] = m;
   __syncthreads();
   if (q != 0) return;
+  if (lane == 0) {
+    float mm = lm[0];
+#pragma unroll
+    for (int k = 1; k < kRQ; ++k) mm = fmaxf(mm, lm[k]);
+    st.mpart[blockIdx.x] = mm;
+  }
   double rpart = 0.0;
   if (g < N) {
     float cs = lc[0][lane], rs = lr[0][lane];
@@ -307,12 +319,11 @@ stream_reduce(StreamState st, int TR, int TC) {
 }
 
 // One workgroup, after stream_reduce: s from the partials in block order,
-// max|dY| over the tiles, the stop test and the pass count.
+// max|dY| from the tile-row maxima, the stop test and the pass count.
 //   ctl: 0 running, 1 converged, 2 non-finite values.
 //   scal[0] = s, scal[1] = last max|dY|; counters[0] = passes done.
 __global__ void __launch_bounds__(kFThreads)
-stream_final(StreamState st, int nparts, int ntiles, int is_pass,
-             double tol) {
+stream_final(StreamState st, int nparts, int is_pass, double tol) {
   if (__hip_atomic_load(st.ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
     return;
   __shared__ double ld[4];
@@ -324,7 +335,7 @@ stream_final(StreamState st, int nparts, int ntiles, int is_pass,
   for (int k = t; k < nparts; k += kFThreads) sp += st.spart[k];
   float m = 0.f;
 #pragma unroll 8
-  for (int k = t; k < ntiles; k += kFThreads) m = fmaxf(m, st.tmax[k]);
+  for (int k = t; k < nparts; k += kFThreads) m = fmaxf(m, st.mpart[k]);
   sp = wave_sum_dd(sp);
   m = wave_max_f(m);
   if (lane == 0) {
@@ -403,6 +414,6 @@ extern "C" hipError_t fpfp_stream_step(const fpfp::StreamState* st, int mode,
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   fpfp::stream_final<<<dim3(1), dim3(fpfp::kFThreads), 0, stream>>>(
-      *st, nrb, TR * TC, mode != 0, tol);
+      *st, nrb, mode != 0, tol);
   return hipGetLastError();
 }

@@ -46,6 +46,7 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
   const size_t nrb = (size_t)nrb_i;  // reduce blocks
   const size_t o_tm = off; off = align256(off + sizeof(float) * nt);
   const size_t o_sp = off; off = align256(off + sizeof(double) * nrb);
+  const size_t o_mp = off; off = align256(off + sizeof(float) * nrb);
   const size_t o_sc = off; off = align256(off + sizeof(double) * 2);
   const size_t o_ct = off; off = align256(off + sizeof(unsigned) * 2);
   const size_t need = off;
@@ -69,6 +70,7 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
   st.colpart = (float*)(base + o_cp);
   st.tmax = (float*)(base + o_tm);
   st.spart = (double*)(base + o_sp);
+  st.mpart = (float*)(base + o_mp);
   st.scal = (double*)(base + o_sc);
   unsigned* cw = (unsigned*)(base + o_ct);
   st.ctl = cw;

@@ -14,6 +14,7 @@ struct StreamState {
   float* colpart;       // [TR][N] column partials of each tile row
   float* tmax;          // [TR * TC] tile max|dY|
   double* spart;        // [nrb] partials of s, one per reduce block
+  float* mpart;         // [nrb] max|dY| of each tile row, one per reduce block
   double* scal;         // [0] s = 1^T Y 1, [1] last max|dY|
   unsigned* counters;   // [0] passes run
   unsigned* ctl;        // 0 running, 1 converged, 2 non-finite

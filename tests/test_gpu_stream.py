@@ -93,3 +93,32 @@ def test_large_n_exact_projection_routes_to_the_stream(env):
     info = S.project(Yg, 1e-30, T, projection=F.DYKSTRA)
     _cmp(info, Yg.cpu().numpy(), O.dykstra_inner(Y.astype(np.float64),
                                                  1e-30, T))
+
+
+@pytest.mark.parametrize("N,T,projection", [(6000, 3, "alternating"),
+                                            (8200, 3, "alternating"),
+                                            (6000, 2, "dykstra")])
+def test_stream_parity_past_the_cache(N, T, projection):
+    """Matrices larger than half (N = 6000, 144 MB) and than all (N = 8200,
+    269 MB) of the 256 MiB last-level cache: the pass reads Y with
+    non-temporal loads, and at 8200 also writes it with non-temporal stores.
+    Both sizes leave ragged tiles (N % 64 and N % 1024 are not 0), so the
+    bounds-checked edge path runs beside the unchecked one.  (Dykstra's pass
+    takes the same accesses with other arithmetic; its float64 oracle is too
+    slow for more than two passes at N = 6000 here.)"""
+    import torch
+    from paper_1207_1114_amd import fastpfp as F
+    rng = np.random.default_rng([N, 23])
+    Y = (rng.random((N, N)) * 2.0 - 0.5).astype(np.float32)
+    proj = {"alternating": F.ALTERNATING, "dykstra": F.DYKSTRA}[projection]
+    inner = {"alternating": O.inner_projection,
+             "dykstra": O.dykstra_inner}[projection]
+    S = F.Solver(N, N)
+    try:
+        Yg = dev(torch, Y)
+        info = S.project_stream(Yg, 1e-30, T, projection=proj)
+        got = Yg.cpu().numpy()
+        del Yg
+    finally:
+        S.close()
+    _cmp(info, got, inner(Y.astype(np.float64), 1e-30, T))
