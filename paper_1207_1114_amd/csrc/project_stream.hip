@@ -9,7 +9,7 @@
 //                 partials and the tile's max|D - Y|;
 //   stream_reduce r_i and c_j from the partials in a fixed order, giving
 //                 (1 - r_i)/N (float64) and b_j = (1 - c_j)/N, and partials
-//                 of s;
+//                 of s and of max|dY|, one per tile row;
 //   stream_final  s = 1^T D 1 (float64, fixed order), max|dY|, the stop test
 //                 (max|dY| < eps2) and the pass count.
 // After the stop test holds, later launches of the same call return at once,
@@ -64,8 +64,9 @@ __device__ __forceinline__ double wave_sum_dd(double v) {
 
 // Y is touched once per pass.  kNT selects how its 16-byte accesses treat
 // the caches: 0 plain, 1 non-temporal loads, 2 non-temporal loads and
-// stores (for a matrix larger than the last-level cache, streaming it past
-// the caches keeps them for the partials and avoids evicting dirty lines).
+// stores; stream_nt_policy picks, by matrix size, the one that measured
+// fastest (non-temporal loads alone, or stores alone, gave nothing for a
+// matrix four times the last-level cache; both together 8%).
 typedef float f4v __attribute__((ext_vector_type(4)));
 template <int kNT>
 __device__ __forceinline__ f4v load_y4(const float* p) {
