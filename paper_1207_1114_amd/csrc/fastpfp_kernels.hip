@@ -241,7 +241,19 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
     const int mm = tid & (kGT - 1), kb = tid / kGT;
     const bool pm = m0 + mm < M, qm = n0 + mm < Nc;
     float pa[kPer], qa[kPer];
+    // a tile inside both operands, at a k-step inside Kd, needs no bounds
+    // checks: its loads are then unconditional and issue together
+    const bool tile_in = m0 + kGT <= M && n0 + kGT <= Nc;
     auto fetch = [&](int k0) {
+      if (tile_in && k0 + kGK <= Kd) {
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int kg = k0 + kb + e * (kThreads / kGT);
+          pa[e] = P[(long long)kg * ldp + m0 + mm];
+          qa[e] = Q[(long long)kg * ldq + n0 + mm];
+        }
+        return;
+      }
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
         const int kg = k0 + kb + e * (kThreads / kGT);
