@@ -549,3 +549,104 @@ def test_pg_is_not_fastpfp_with_unit_alpha():
     # gradient 0: FastPFP projects 0 (uniform 1/n), PG projects X0 itself
     np.testing.assert_allclose(f0.X, np.full((n, n), 1.0 / n), atol=1e-10)
     np.testing.assert_allclose(g0.X, O.dykstra_projection(X0), atol=1e-10)
+
+
+# ------------------------------------ slack carry-over and eps1 (Alg. 1)
+def _n2_hand_trajectory(a, B, lam, K, alpha, steps, rows):
+    """Algorithm 1 on a pair with min(n, n') = 1, max(n, n') = 2, written
+    out by hand through the N = 2 closed form of the inner loop.
+
+    rows=True: n = 1, n' = 2 (X is 1 x 2, the slack is row 1 of Y);
+    rows=False: n = 2, n' = 1 (X is 2 x 1, the slack is column 1 of Y).
+    The gradient (Sec. 4.1) goes to the leading block, the slack keeps the
+    values the previous step left (steps 1 and 3: Y is set to 0 once and
+    step 3 overwrites only the leading block).  With the four entries of Y
+    the first P1 gives [[q, 1-q], [1-q, q]], q = 1/2 + (y11 - y12 - y21 +
+    y22)/4; for 0 <= q <= 1 the clamp leaves it and the second pass moves
+    nothing, so the loop returns it after two passes.  Then step 8 (damped
+    update), step 9 (divide by the maximum) and eps1 between the stored,
+    normalised iterates (at t = 1 against X0 itself).
+
+    Returns the q of every step, the iterates, eps1 trace and last slack.
+    """
+    x = [0.5, 0.5]                 # X0 = c 1 1^T with c = 1/max(n, n')
+    s = [0.0, 0.0]                 # slack entries, Y = 0 at the start
+    qs, xs, e1s = [], [], []
+    for _ in range(steps):
+        if rows:     # g = a * X B + lam K, X a row vector
+            g = [a * (x[0] * B[0][0] + x[1] * B[1][0]) + lam * K[0],
+                 a * (x[0] * B[0][1] + x[1] * B[1][1]) + lam * K[1]]
+            # Y = [[g0, g1], [s0, s1]]
+            q = 0.5 + (g[0] - g[1] - s[0] + s[1]) / 4.0
+        else:        # g = A X b + lam K, X a column vector, A 2 x 2, b = a
+            g = [a * (B[0][0] * x[0] + B[0][1] * x[1]) + lam * K[0],
+                 a * (B[1][0] * x[0] + B[1][1] * x[1]) + lam * K[1]]
+            # Y = [[g0, s0], [g1, s1]]
+            q = 0.5 + (g[0] - s[0] - g[1] + s[1]) / 4.0
+        assert 0.0 < q < 1.0       # the unclamped case of the closed form
+        qs.append(q)
+        lead = [q, 1.0 - q]        # X block of [[q, 1-q], [1-q, q]]
+        s = [1.0 - q, q]           # the other row (column) is the slack
+        xn = [(1 - alpha) * x[k] + alpha * lead[k] for k in range(2)]
+        mx = max(xn)
+        xn = [v / mx for v in xn]
+        e1s.append(max(abs(xn[k] - x[k]) for k in range(2)))
+        x = xn
+        xs.append(list(x))
+    return qs, xs, e1s, s
+
+
+@pytest.mark.parametrize("rows", [True, False])
+def test_slack_carries_over_between_outer_steps(rows):
+    """Algorithm 1, steps 1 and 3: the slack block of Y persists from one
+    outer step to the next.  The trajectory is the hand recursion above; a
+    solver that clears the slack before each step gives q_t smaller by
+    (2 q_{t-1} - 1)/4 from t = 2 on (0.025 at t = 2 here) and fails."""
+    a, lam, alpha = 1.0, 0.5, 0.5
+    Bm = [[0.3, 0.1], [0.1, 0.2]]
+    Kv = [0.4, 0.1]
+    steps = 6
+    qs, xs, e1s, s = _n2_hand_trajectory(a, Bm, lam, Kv, alpha, steps, rows)
+    if rows:
+        A, B, K = np.array([[a]]), np.array(Bm), np.array([Kv])
+    else:
+        A, B, K = np.array(Bm), np.array([[a]]), np.array([Kv]).T
+    r = O.fastpfp(A, B, K, lam, alpha=alpha, eps1=0.0, max_outer=steps,
+                  eps2=1e-12, max_inner=50)
+    assert r.inner_iters == [2] * steps
+    want_x = np.array(xs[-1]).reshape(r.X.shape)
+    np.testing.assert_allclose(r.X, want_x, atol=1e-13)
+    np.testing.assert_allclose(r.eps1_trace, e1s, atol=1e-13)
+    Yend = np.array([[qs[-1], 1 - qs[-1]], [1 - qs[-1], qs[-1]]])
+    np.testing.assert_allclose(r.slack, Yend, atol=1e-13)
+    # the carried slack moves the iterate: q_2 differs from the value a
+    # cleared slack would give by (2 q_1 - 1) / 4
+    assert abs(2 * qs[0] - 1) / 4 > 0.02
+
+
+@pytest.mark.parametrize("rows", [True, False])
+def test_eps1_is_measured_after_step9(rows):
+    """Sec. 5 (convergence criteria) with step 9 of Algorithm 1: eps1 is
+    max|X_{t+1} - X_t| between the normalised iterates.  At t = 1 it is
+    |X_1 - X0| = 1 - 1/2 here (the largest entry becomes 1), while the
+    change before normalising is alpha |q_1 - 1/2| = 0.025; the outer loop
+    stops at the first step whose normalised change is below eps1."""
+    a, lam, alpha = 1.0, 0.5, 0.5
+    Bm = [[0.3, 0.1], [0.1, 0.2]]
+    Kv = [0.4, 0.1]
+    qs, xs, e1s, _ = _n2_hand_trajectory(a, Bm, lam, Kv, alpha, 12, rows)
+    assert abs(e1s[0] - 0.5) < 1e-15
+    if rows:
+        A, B, K = np.array([[a]]), np.array(Bm), np.array([Kv])
+    else:
+        A, B, K = np.array(Bm), np.array([[a]]), np.array([Kv]).T
+    # eps1 halfway (geometrically) between the 3rd and 4th normalised
+    # changes: the loop must stop after exactly 4 steps
+    eps1 = float(np.sqrt(e1s[2] * e1s[3]))
+    assert e1s[3] < eps1 < e1s[2]
+    r = O.fastpfp(A, B, K, lam, alpha=alpha, eps1=eps1, max_outer=50,
+                  eps2=1e-12, max_inner=50)
+    assert r.outer_iters == 4 and r.converged
+    np.testing.assert_allclose(r.eps1_trace, e1s[:4], atol=1e-13)
+    np.testing.assert_allclose(r.X, np.array(xs[3]).reshape(r.X.shape),
+                               atol=1e-13)
