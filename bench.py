@@ -148,6 +148,7 @@ def ragged_batch(torch, F, steps):
         infos = S.solve_batched(*args)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    S.close()
     Xall = d["X"].cpu().numpy().ravel()
     acc = []
     for p, o in zip(pairs, offs["X"]):
@@ -443,7 +444,7 @@ def main():
                    "team_size": team,
                    "team_size_from": "autotuner" if tuned else "argument"},
         "roofline": {"bound": "alu", "achieved": achieved,
-                     "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "peak": ALU_PEAK_TOPS, "unit": "T ops/s",
                      "frac": achieved / ALU_PEAK_TOPS,
                      "traffic": traffic_bytes(args, team),
                      "kernel": "fastpfp_persistent",

@@ -446,9 +446,16 @@ def main():
     betas = [float(v) for v in a.betas.split(",")]
     rep = evaluate(raw, sizes, betas)
     os.makedirs(a.out, exist_ok=True)
-    np.save(os.path.join(a.out, "warmstart_params_raw.npy"), raw)
-    deployed = sharpened(raw, rep["beta"] if rep["accepted"] else 1.0)
+    beta = rep["beta"] if rep["accepted"] else 1.0
+    deployed = sharpened(raw, beta)
     np.save(os.path.join(a.out, "warmstart_params.npy"), deployed)
+    # the trained (unsharpened) parameters only when they differ from the
+    # deployed ones
+    raw_path = os.path.join(a.out, "warmstart_params_raw.npy")
+    if beta != 1.0:
+        np.save(raw_path, raw)
+    elif os.path.exists(raw_path):
+        os.remove(raw_path)
     meta = {"accepted": rep["accepted"], "beta": rep["beta"],
             "evaluation": rep,
             "training": {k: v for k, v in log.items() if k != "history"},
