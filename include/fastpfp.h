@@ -127,7 +127,9 @@ fastpfp_status fastpfp_params_default(fastpfp_params* p);
 
 /* Creates a handle bound to HIP device `device` and to `hip_stream` (a
  * hipStream_t; NULL = the null stream).  max_n / max_np bound the sizes
- * later calls may pass (>= 1).  No device memory is allocated here. */
+ * later calls may pass (>= 1).  No device memory is allocated here; the
+ * first handle on a device looks up that device's fixed scratch array of
+ * fastpfp_solve_noalloc. */
 fastpfp_status fastpfp_create(fastpfp_t* h, int device, int max_n, int max_np,
                               void* hip_stream);
 fastpfp_status fastpfp_destroy(fastpfp_t h);
@@ -154,6 +156,31 @@ fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np,
                              float* X, int ldx,
                              float* Y_state,
                              fastpfp_info* info);
+
+/* fastpfp_solve without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and meaning as fastpfp_solve, and the
+ * same kernels, so the results are bitwise those of fastpfp_solve with the
+ * same team size.  Limit: max(n, n') <= FASTPFP_NOALLOC_MAX_N.
+ * Instead of the handle's workspace the call uses a library-owned device
+ * array of FASTPFP_NOALLOC_SCRATCH_BYTES per GPU (each GPU the library runs
+ * on holds it until the process ends); what must start at zero is cleared by
+ * a kernel on every call, and nothing is allocated or freed.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (from any
+ * handle or host thread) race, so the caller must serialise them.
+ * Errors: SHAPE when max(n, n') > FASTPFP_NOALLOC_MAX_N or the launch's
+ * workspace would not fit the array; otherwise those of fastpfp_solve.
+ * Does not record the eps1 trace that fastpfp_get_trace returns. */
+#define FASTPFP_NOALLOC_MAX_N 1024
+#define FASTPFP_NOALLOC_SCRATCH_BYTES (17u << 20)
+fastpfp_status fastpfp_solve_noalloc(fastpfp_t h, int n, int np,
+                                     const float* A, int lda,
+                                     const float* B, int ldb,
+                                     const float* K, int ldk,
+                                     const fastpfp_params* p,
+                                     float* X, int ldx,
+                                     float* Y_state,
+                                     fastpfp_info* info);
 
 /* Solves `batch` independent pairs in one persistent launch.
  *   n_host[b], np_host[b]: sizes of pair b.

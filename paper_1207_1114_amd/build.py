@@ -28,7 +28,8 @@ HIP_SOURCES = [("fastpfp_kernels.hip", "fastpfp_kernels", []),
                 ["-DFPFP_DYKSTRA_BUILD=1"]),
                ("warmstart.hip", "warmstart", []),
                ("discretize_device.hip", "discretize_device", []),
-               ("project_stream.hip", "project_stream", [])]
+               ("project_stream.hip", "project_stream", []),
+               ("noalloc.hip", "noalloc", [])]
 CXX_SOURCES = ["fastpfp_api.cpp", "warmstart_api.cpp", "discretize.cpp",
                "discretize_device_api.cpp", "project_stream_api.cpp"]
 

@@ -23,6 +23,12 @@ extern "C" hipError_t fpfp_launch_persistent_dykstra(const fpfp::LaunchDesc* L,
                                                      int grid,
                                                      hipStream_t stream);
 extern "C" hipError_t fpfp_occupancy_dykstra(int* blocks_per_cu);
+// The fixed scratch of fastpfp_solve_noalloc (noalloc.hip).
+extern "C" hipError_t fpfp_noalloc_scratch(int device, void** ptr,
+                                           size_t* bytes);
+extern "C" hipError_t fpfp_noalloc_prepare(const fpfp::PairDesc* d, void* dst,
+                                           void* zero, size_t bytes,
+                                           hipStream_t stream);
 
 namespace {
 
@@ -160,6 +166,92 @@ struct PairIn {
   int lda, ldb, ldk, ldx;
 };
 
+// The device descriptor of one pair.
+void fill_pair(fpfp::PairDesc* dp, const PairIn& q, const fastpfp_params* p,
+               int mode, int max_inner, double tol_in, float* trace,
+               fpfp::DevInfo* info) {
+  fpfp::PairDesc& d = *dp;
+  std::memset(&d, 0, sizeof d);
+  d.A = q.A;
+  d.B = q.B;
+  d.K = (p && p->lambda > 0.0) ? q.K : nullptr;
+  d.X = q.X;
+  d.Y = q.Y;
+  d.trace = trace;
+  d.info = info;
+  d.n = q.n;
+  d.np = q.np;
+  d.N = std::max(q.n, q.np);
+  d.lda = q.lda;
+  d.ldb = q.ldb;
+  d.ldk = q.ldk;
+  d.ldx = q.ldx;
+  d.mode = mode;
+  d.max_inner = max_inner;
+  d.tol_in = (float)tol_in;
+  if (mode == fpfp::kModeSolve) {
+    d.init_user = p->init == FASTPFP_INIT_USER;
+    d.y_user = q.Y != nullptr;
+    d.normalize = p->normalize_max != 0;
+    d.max_outer = p->max_outer;
+    d.precision = p->precision;
+    d.lam = (float)p->lambda;
+    // Projected Gradient: step 3 forms X + alpha * gradient and step 8
+    // takes the projection undamped
+    const bool pg = p->method == FASTPFP_METHOD_PG;
+    d.alpha = pg ? 1.0f : (float)p->alpha;
+    d.pg_step = pg ? (float)p->alpha : 0.0f;
+    d.tol_out = (float)p->tol_outer;
+    d.init_c = (float)(p->init_scale > 0.0 ? p->init_scale
+                                           : 1.0 / (double)d.N);
+  } else {
+    d.y_user = 1;
+  }
+}
+
+// The launch descriptor over a workspace at `base` laid out as `lay`.
+void fill_launch(fpfp::LaunchDesc* Lp, fastpfp_t h, char* base,
+                 const Layout& lay, int P, int NG, const fpfp::TeamGroup* grp,
+                 int maxN) {
+  fpfp::LaunchDesc& L = *Lp;
+  std::memset(&L, 0, sizeof L);
+  L.pairs = (const fpfp::PairDesc*)(base + lay.pairs);
+  L.num_pairs = P;
+  L.num_groups = NG;
+  for (int g = 0; g < NG; ++g) L.group[g] = grp[g];
+  L.max_N = maxN;
+  L.cus_per_xcd = std::max(1, h->cu_count / fpfp::kXcds);
+  L.xbuf = (uint64_t*)(base + lay.xbuf);
+  L.xbuf_stride = lay.xbuf_stride;
+  L.wsT = (float*)(base + lay.wsT);
+  L.wsT_stride = lay.wsT_stride;
+  L.wsY = (float*)(base + lay.wsY);
+  L.wsY_stride = lay.wsY_stride;
+  L.wsH = (uint16_t*)(base + lay.wsH);
+  L.wsH_stride = lay.wsH_stride;
+  L.queue = (unsigned*)(base + lay.queue);
+  L.timeout_ticks = 100000000LL * 20;  // 20 s of the 100 MHz wall clock
+}
+
+// Copies one pair's device result into the public info struct.
+void copy_info(fastpfp_info* o, const fpfp::DevInfo& d, float ms) {
+  o->outer_iters = d.outer;
+  o->inner_iters_total = d.inner_total;
+  o->inner_iters_max = d.inner_max;
+  o->inner_capped = d.inner_capped;
+  o->converged = d.converged;
+  o->status = d.status;
+  o->eps1_last = d.eps1;
+  o->eps2_last = d.eps2;
+  o->kernel_ms = ms;
+}
+
+// Usable workgroups of one cooperative launch (a multiple of the XCD count).
+int launch_grid(fastpfp_t h) {
+  int G = std::min(512, h->occupancy * h->cu_count);
+  return G - G % fpfp::kXcds;
+}
+
 // Plans, launches and waits for one persistent launch over `pairs`.
 fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                    const fastpfp_params* p, int mode, int max_inner,
@@ -183,8 +275,7 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                   team_req, Nb);
     }
   }
-  int G = std::min(512, h->occupancy * h->cu_count);
-  G -= G % fpfp::kXcds;
+  const int G = launch_grid(h);
   std::vector<int> sizes;
   for (auto& q : pplan)
     if (std::find(sizes.begin(), sizes.end(), q.W) == sizes.end())
@@ -282,63 +373,12 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
   std::vector<fpfp::PairDesc> pd(P);
   for (int k = 0; k < P; ++k) {
     const int b = order[k];
-    const PairIn& q = pairs[b];
-    fpfp::PairDesc& d = pd[k];
-    std::memset(&d, 0, sizeof d);
-    d.A = q.A;
-    d.B = q.B;
-    d.K = (p && p->lambda > 0.0) ? q.K : nullptr;
-    d.X = q.X;
-    d.Y = q.Y;
-    d.trace = (want_trace && b == 0) ? (float*)(base + lay.trace) : nullptr;
-    d.info = (fpfp::DevInfo*)(base + lay.infos) + b;
-    d.n = q.n;
-    d.np = q.np;
-    d.N = std::max(q.n, q.np);
-    d.lda = q.lda;
-    d.ldb = q.ldb;
-    d.ldk = q.ldk;
-    d.ldx = q.ldx;
-    d.mode = mode;
-    d.max_inner = max_inner;
-    d.tol_in = (float)tol_in;
-    if (mode == fpfp::kModeSolve) {
-      d.init_user = p->init == FASTPFP_INIT_USER;
-      d.y_user = q.Y != nullptr;
-      d.normalize = p->normalize_max != 0;
-      d.max_outer = p->max_outer;
-      d.precision = p->precision;
-      d.lam = (float)p->lambda;
-      // Projected Gradient: step 3 forms X + alpha * gradient and step 8
-      // takes the projection undamped
-      const bool pg = p->method == FASTPFP_METHOD_PG;
-      d.alpha = pg ? 1.0f : (float)p->alpha;
-      d.pg_step = pg ? (float)p->alpha : 0.0f;
-      d.tol_out = (float)p->tol_outer;
-      d.init_c = (float)(p->init_scale > 0.0 ? p->init_scale
-                                             : 1.0 / (double)d.N);
-    } else {
-      d.y_user = 1;
-    }
+    fill_pair(&pd[k], pairs[b], p, mode, max_inner, tol_in,
+              (want_trace && b == 0) ? (float*)(base + lay.trace) : nullptr,
+              (fpfp::DevInfo*)(base + lay.infos) + b);
   }
   fpfp::LaunchDesc L;
-  std::memset(&L, 0, sizeof L);
-  L.pairs = (const fpfp::PairDesc*)(base + lay.pairs);
-  L.num_pairs = P;
-  L.num_groups = NG;
-  for (int g = 0; g < NG; ++g) L.group[g] = grp[g];
-  L.max_N = maxN;
-  L.cus_per_xcd = std::max(1, h->cu_count / fpfp::kXcds);
-  L.xbuf = (uint64_t*)(base + lay.xbuf);
-  L.xbuf_stride = lay.xbuf_stride;
-  L.wsT = (float*)(base + lay.wsT);
-  L.wsT_stride = lay.wsT_stride;
-  L.wsY = (float*)(base + lay.wsY);
-  L.wsY_stride = lay.wsY_stride;
-  L.wsH = (uint16_t*)(base + lay.wsH);
-  L.wsH_stride = lay.wsH_stride;
-  L.queue = (unsigned*)(base + lay.queue);
-  L.timeout_ticks = 100000000LL * 20;  // 20 s of the 100 MHz wall clock
+  fill_launch(&L, h, base, lay, P, NG, grp.data(), maxN);
 
   HIPCHK(h, hipMemcpyAsync(base + lay.pairs, pd.data(),
                            sizeof(fpfp::PairDesc) * pd.size(),
@@ -375,23 +415,91 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                 "a device-side wait exceeded its limit; results are invalid");
   fastpfp_status first = FASTPFP_OK;
   for (size_t b = 0; b < di.size(); ++b) {
-    fastpfp_info& o = infos[b];
-    o.outer_iters = di[b].outer;
-    o.inner_iters_total = di[b].inner_total;
-    o.inner_iters_max = di[b].inner_max;
-    o.inner_capped = di[b].inner_capped;
-    o.converged = di[b].converged;
-    o.status = di[b].status;
-    o.eps1_last = di[b].eps1;
-    o.eps2_last = di[b].eps2;
-    o.kernel_ms = ms;
-    if (o.status != 0 && first == FASTPFP_OK) first = (fastpfp_status)o.status;
+    copy_info(&infos[b], di[b], ms);
+    if (infos[b].status != 0 && first == FASTPFP_OK)
+      first = (fastpfp_status)infos[b].status;
   }
   if (want_trace) {
     h->trace.assign(tr.begin(), tr.begin() + std::min<int>(di[0].outer, max_outer));
   }
   if (first != FASTPFP_OK)
     return fail(h, first, "non-finite values met during the solve");
+  return FASTPFP_OK;
+}
+
+// One pair, one team, with the workspace in the device's fixed scratch
+// array instead of the handle's: the same plan, descriptors and kernel as
+// run() gives a single pair, and no allocation.  The descriptor is written
+// and the counters cleared by a kernel.
+fastpfp_status run_noalloc(fastpfp_t h, const PairIn& q,
+                           const fastpfp_params* p, fastpfp_info* info) {
+  HIPCHK(h, hipSetDevice(h->device));
+  void* scratch = nullptr;
+  size_t cap = 0;
+  HIPCHK(h, fpfp_noalloc_scratch(h->device, &scratch, &cap));
+  const int N = std::max(q.n, q.np);
+  Plan pl;
+  if (!plan_team(N, p->team_size, &pl)) {
+    if (p->team_size == 0)
+      return fail(h, FASTPFP_ERR_UNSUPPORTED,
+                  "N = %d exceeds the largest team's tiles", N);
+    return fail(h, FASTPFP_ERR_INVALID_ARG,
+                "team_size %d is not a power of two whose tiles fit N = %d",
+                p->team_size, N);
+  }
+  const int G = launch_grid(h);
+  if (pl.W > G)
+    return fail(h, FASTPFP_ERR_UNSUPPORTED,
+                "a team of %d workgroups does not fit the %d co-resident ones",
+                pl.W, G);
+  fpfp::TeamGroup grp;
+  grp.W = pl.W;
+  grp.TR = pl.TR;
+  grp.TC = pl.TC;
+  grp.num_teams = 1;
+  grp.v_begin = 0;
+  grp.team_base = 0;
+  grp.pair_begin = 0;
+  grp.pair_end = 1;
+  const long long xwords = fpfp::xbuf_words_per_parity(pl.TR, pl.TC, pl.W, N);
+  const Layout lay = layout_for(1, 1, xwords, N, q.n * q.np, p->max_outer,
+                                q.Y == nullptr, false,
+                                p->precision == FASTPFP_BF16, 1);
+  if (lay.total > cap)
+    return fail(h, FASTPFP_ERR_SHAPE,
+                "the solve needs %zu bytes of scratch; the fixed array has %zu",
+                lay.total, cap);
+  char* base = (char*)scratch;
+  fpfp::PairDesc d;
+  fill_pair(&d, q, p, fpfp::kModeSolve, p->max_inner, p->tol_inner, nullptr,
+            (fpfp::DevInfo*)(base + lay.infos));
+  fpfp::LaunchDesc L;
+  fill_launch(&L, h, base, lay, 1, 1, &grp, N);
+  // per-pair results, queue, (empty) trace and exchange words are
+  // contiguous in the layout and all start at zero
+  HIPCHK(h, fpfp_noalloc_prepare(&d, base + lay.pairs, base + lay.infos,
+                                 lay.wsT - lay.infos, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev0, h->stream));
+  HIPCHK(h, p->projection == FASTPFP_PROJ_DYKSTRA
+                ? fpfp_launch_persistent_dykstra(&L, G, h->stream)
+                : fpfp_launch_persistent(&L, G, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev1, h->stream));
+  fpfp::DevInfo di;
+  unsigned abort_flag = 0;
+  HIPCHK(h, hipMemcpyAsync(&di, base + lay.infos, sizeof di,
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&abort_flag, base + lay.queue, sizeof abort_flag,
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  float ms = 0.f;
+  HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (abort_flag != 0)
+    return fail(h, FASTPFP_ERR_TIMEOUT,
+                "a device-side wait exceeded its limit; results are invalid");
+  copy_info(info, di, ms);
+  if (di.status != 0)
+    return fail(h, (fastpfp_status)di.status,
+                "non-finite values met during the solve");
   return FASTPFP_OK;
 }
 
@@ -466,6 +574,16 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
   }
   // launches size their grids for the kernel that fits fewer workgroups
   h->occupancy = std::min(h->occupancy, occ_dyk);
+  // the device address of this device's fixed scratch array (looked up once
+  // per device, with the device current)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  if (fpfp_noalloc_scratch(device, &scratch, &scratch_bytes) != hipSuccess) {
+    (void)hipEventDestroy(h->ev0);
+    (void)hipEventDestroy(h->ev1);
+    delete h;
+    return FASTPFP_ERR_HIP;
+  }
   *out = h;
   return FASTPFP_OK;
 }
@@ -507,6 +625,37 @@ fastpfp_status fastpfp_solve(fastpfp_t h, int n, int np, const float* A,
   st = run(h, pairs, p, fpfp::kModeSolve, p->max_inner, p->tol_inner,
            p->projection,
            p->team_size, true, &tmp);
+  if (info) *info = tmp;
+  return st;
+}
+
+fastpfp_status fastpfp_solve_noalloc(fastpfp_t h, int n, int np,
+                                     const float* A, int lda, const float* B,
+                                     int ldb, const float* K, int ldk,
+                                     const fastpfp_params* p, float* X,
+                                     int ldx, float* Y_state,
+                                     fastpfp_info* info) {
+  if (!h) return FASTPFP_ERR_INVALID_ARG;
+  fastpfp_status st = check_params(h, p);
+  if (st != FASTPFP_OK) return st;
+  if (n < 1 || np < 1 || n > h->max_n || np > h->max_np)
+    return fail(h, FASTPFP_ERR_SHAPE, "n=%d n'=%d outside [1, %d] x [1, %d]",
+                n, np, h->max_n, h->max_np);
+  if (std::max(n, np) > FASTPFP_NOALLOC_MAX_N)
+    return fail(h, FASTPFP_ERR_SHAPE,
+                "max(n, n') = %d exceeds the allocation-free limit %d",
+                std::max(n, np), FASTPFP_NOALLOC_MAX_N);
+  if (!A || !B || !X)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "A, B and X must be non-NULL");
+  if (p->lambda > 0.0 && !K)
+    return fail(h, FASTPFP_ERR_INVALID_ARG, "K is NULL but lambda > 0");
+  if (bad_ld(lda, n) || bad_ld(ldb, np) || bad_ld(ldx, np) ||
+      (p->lambda > 0.0 && bad_ld(ldk, np)))
+    return fail(h, FASTPFP_ERR_SHAPE, "a leading dimension is too small");
+  const PairIn q{n, np, A, B, K, X, Y_state, lda, ldb, ldk, ldx};
+  fastpfp_info tmp;
+  std::memset(&tmp, 0, sizeof tmp);
+  st = run_noalloc(h, q, p, &tmp);
   if (info) *info = tmp;
   return st;
 }
@@ -596,8 +745,7 @@ fastpfp_status fastpfp_autotune(fastpfp_t h, int N, int batch, int passes,
   Plan pl;
   if (!plan_team(N, 0, &pl))
     return fail(h, FASTPFP_ERR_UNSUPPORTED, "N=%d fits no team", N);
-  int G = std::min(512, h->occupancy * h->cu_count);
-  G -= G % fpfp::kXcds;
+  const int G = launch_grid(h);
   std::vector<int> cand;
   for (int W = pl.W; W <= std::min(G, fpfp::kMaxTeam); W *= 2) cand.push_back(W);
   if (cand.empty())

@@ -31,7 +31,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           7: "unsupported request"}
 
 EXPORTS = ("fastpfp_params_default", "fastpfp_create", "fastpfp_destroy",
-           "fastpfp_solve", "fastpfp_solve_batched", "fastpfp_project",
+           "fastpfp_solve", "fastpfp_solve_noalloc", "fastpfp_solve_batched",
+           "fastpfp_project",
            "fastpfp_discretize_greedy_batched", "fastpfp_project_stream",
            "fastpfp_discretize", "fastpfp_get_trace", "fastpfp_status_string",
            "fastpfp_last_error", "fastpfp_abi_version",
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_destroy.argtypes = [P]
     lib.fastpfp_solve.argtypes = [P, I, I, P, I, P, I, P, I, L(Params), P, I,
                                   P, L(Info)]
+    lib.fastpfp_solve_noalloc.argtypes = lib.fastpfp_solve.argtypes
     lib.fastpfp_solve_batched.argtypes = [P, I, P, P, P, P, P, P, P, P,
                                           L(Params), P, P, P]
     lib.fastpfp_project.argtypes = [P, I, P, ctypes.c_double, I, I, I,
@@ -113,7 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastpfp_last_error.argtypes = [P]
     lib.fastpfp_last_error.restype = ctypes.c_char_p
     for name in ("fastpfp_params_default", "fastpfp_create",
-                 "fastpfp_destroy", "fastpfp_solve", "fastpfp_solve_batched",
+                 "fastpfp_destroy", "fastpfp_solve", "fastpfp_solve_noalloc",
+                 "fastpfp_solve_batched",
                  "fastpfp_project", "fastpfp_discretize",
                  "fastpfp_get_trace", "fastpfp_abi_version",
                  "fastpfp_warmstart_load", "fastpfp_warmstart_get",
@@ -201,16 +204,25 @@ class Solver:
 
     def solve(self, A, B, K, X, params: Params, Y_state=None) -> dict:
         """In-place solve of one pair; X holds X0 (INIT_USER) and the result."""
+        return self._solve(self._lib.fastpfp_solve, A, B, K, X, params,
+                           Y_state)
+
+    def solve_noalloc(self, A, B, K, X, params: Params, Y_state=None) -> dict:
+        """solve() through fastpfp_solve_noalloc: no device allocation, the
+        library's fixed per-device scratch instead (max(n, n') <= 1024)."""
+        return self._solve(self._lib.fastpfp_solve_noalloc, A, B, K, X,
+                           params, Y_state)
+
+    def _solve(self, fn, A, B, K, X, params, Y_state) -> dict:
         for t, nm in ((A, "A"), (B, "B"), (K, "K"), (X, "X"),
                       (Y_state, "Y_state")):
             _check_dev(t, nm)
         n, np_ = A.shape[0], B.shape[0]
         info = Info()
-        st = self._lib.fastpfp_solve(
-            self._h, n, np_, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
-            _ptr(K), K.stride(0) if K is not None else 0,
-            ctypes.byref(params), _ptr(X), X.stride(0), _ptr(Y_state),
-            ctypes.byref(info))
+        st = fn(self._h, n, np_, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                _ptr(K), K.stride(0) if K is not None else 0,
+                ctypes.byref(params), _ptr(X), X.stride(0), _ptr(Y_state),
+                ctypes.byref(info))
         if st != 0:
             self._raise(st)
         return info.as_dict()
