@@ -13,11 +13,18 @@ chip, so ``achieved`` counts 7 float32 operations per entry per pass (P1: 2
 adds, P2: 1 max, row/column sums: 2 adds, max|dY|: 1 sub + 1 max) over the
 kernel's average launch time measured with HIP events on the library's
 stream; ``traffic`` is the HBM bytes of one launch from counter runs.
-Further legs on the same pairs: ``bf16`` (BF16 products, uniform start),
-``bf16_warmstart`` (BF16 products from the learned start, the batched warm
-start inside the timed step, uniform re-solve of any pair it fails), and
-``config3`` (512 ragged pairs in one launch).  ``cpu_baseline`` times the
-FP64 oracle on a bounded sample.
+Further legs on the same pairs: ``fp32_tol_5e-4`` (FP32 at the BF16 legs'
+eps1, the control that separates the tolerance from the precision),
+``bf16`` (BF16 products, uniform start), ``bf16_warmstart`` (BF16 products
+from the learned start, the batched warm start inside the timed step,
+uniform re-solve of any pair it fails; its speed-up split into tolerance,
+BF16 and learned-start factors).  Other workloads: ``config2`` (one
+n = 1000 x 1200 pair with outliers), ``config4`` (n = 2000, plain against
+BF16 + learned start) and ``config3`` (512 ragged pairs in one launch).
+Every leg that has a stored FP64 oracle run reports its error against it on
+every entry; ``phases`` gives the per-pair team time of step 3, steps 4-7
+and the rest from device clock stamps, and the products' rate within step
+3.  ``cpu_baseline`` times full FP64 oracle solves on the host.
 """
 from __future__ import annotations
 
@@ -55,8 +62,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1000)
     ap.add_argument("--team-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-passes", type=int, default=4000,
-                    help="inner passes of the oracle timed for the baseline")
+    ap.add_argument("--cpu-passes", type=int, default=300,
+                    help="inner passes of the one-thread oracle sample")
+    ap.add_argument("--cpu-repeats", type=int, default=1,
+                    help="full oracle solves timed (median reported)")
     ap.add_argument("--stream-only", action="store_true",
                     help="run only the streaming-projection leg (N = 8192, "
                          "16384) and an in-place elementwise add on the same "
@@ -86,39 +95,55 @@ def make_inputs(torch, n_pairs, n):
     return pairs, A.view(-1, 1), B.view(-1, 1), K.view(-1, 1), X.view(-1, 1), offs
 
 
-def cpu_baseline(pair, gpu_infos, passes):
-    """Oracle time of one full pair, projected from a timed sample: one
-    outer step's two products plus `passes` inner passes of the FP64 oracle
-    on pair 0, scaled by the outer / inner counts the solve needed."""
+def cpu_baseline(pair, gpu_infos, passes, repeats):
+    """The FP64 oracle on the host: `repeats` full solves of config-1 pair 0
+    (median reported), all host cores for the products (NumPy's elementwise
+    passes run on one thread), and a one-thread figure from a bounded sample
+    (one gradient and `passes` inner passes with BLAS held to one thread,
+    scaled to the pair's outer / inner counts)."""
     from oracle import fastpfp_oracle as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         blas_threads = max([d.get("num_threads", 1)
                             for d in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         blas_threads = os.cpu_count()
-    n, m = pair.n, pair.np_
-    X = O.uniform_x0(n, m)
-    t0 = time.perf_counter()
-    G = O.gradient(pair.A, X, pair.B, pair.K, pair.lam)
-    t_gemm = time.perf_counter() - t0
-    Y = np.zeros((max(n, m), max(n, m)))
-    Y[:n, :m] = G
-    t0 = time.perf_counter()
-    O.inner_projection(Y, 0.0 + 1e-300, passes)
-    t_pass = (time.perf_counter() - t0) / passes
-    outer = gpu_infos[0]["outer_iters"]
-    inner = gpu_infos[0]["inner_iters_total"]
-    t_pair = outer * t_gemm + inner * t_pass
+    times, r = [], None
+    for _ in range(max(1, repeats)):
+        t0 = time.perf_counter()
+        r = O.fastpfp(pair.A, pair.B, pair.K, pair.lam)
+        times.append(time.perf_counter() - t0)
+    t_pair = float(np.median(times))
+    one = None
+    if threadpool_limits is not None:
+        n, m = pair.n, pair.np_
+        with threadpool_limits(limits=1):
+            X = O.uniform_x0(n, m)
+            t0 = time.perf_counter()
+            G = O.gradient(pair.A, X, pair.B, pair.K, pair.lam)
+            t_gemm = time.perf_counter() - t0
+            Y = np.zeros((max(n, m), max(n, m)))
+            Y[:n, :m] = G
+            t0 = time.perf_counter()
+            O.inner_projection(Y, 1e-300, passes)
+            t_pass = (time.perf_counter() - t0) / passes
+        one = 1.0 / (r.outer_iters * t_gemm + sum(r.inner_iters) * t_pass)
     return {"value": 1.0 / t_pair, "unit": "pairs/s",
             "cores": int(blas_threads), "kind": "oracle",
-            "sample": (f"FP64 oracle on config-1 pair 0: 1 gradient "
-                       f"({t_gemm:.3f} s) + {passes} inner passes "
-                       f"({t_pass * 1e3:.2f} ms each), projected to the pair's "
-                       f"{outer} outer steps / {inner} inner passes; "
-                       f"elementwise NumPy runs on 1 thread, products on "
-                       f"{blas_threads} BLAS threads"),
-            "seconds_per_pair": t_pair}
+            "sample": (f"FP64 oracle, full solve of config-1 pair 0 "
+                       f"({r.outer_iters} outer steps, {sum(r.inner_iters)} "
+                       f"inner passes), median of {len(times)}: "
+                       f"{t_pair:.1f} s; products on {blas_threads} BLAS "
+                       f"threads, elementwise NumPy on 1 thread"),
+            "seconds_per_pair": t_pair, "runs_s": times,
+            "one_thread_pairs_per_s": one,
+            "one_thread_sample": (f"1 gradient + {passes} inner passes with "
+                                  "BLAS on 1 thread, scaled to the same "
+                                  "outer / inner counts"),
+            "gpu_outer_iters": int(gpu_infos[0]["outer_iters"]),
+            "gpu_inner_iters": int(gpu_infos[0]["inner_iters_total"]),
+            "host_cpu_count": os.cpu_count()}
 
 
 def ragged_batch(torch, F, steps):
@@ -156,7 +181,15 @@ def ragged_batch(torch, F, steps):
         acc.append(scores.accuracy(m, p.perm))
     flops = sum(2.0 * p.n * p.np_ * (p.n + p.np_) * i["outer_iters"]
                 for p, i in zip(pairs, infos))
+    # ALU roofline of the launch: 7 operations per entry of each pair's own
+    # N x N matrix per inner pass (the padding of its tiles not counted)
+    ops = sum(OPS_PER_ENTRY_PASS * float(max(p.n, p.np_)) ** 2
+              * i["inner_iters_total"] for p, i in zip(pairs, infos))
+    alu = ops / (infos[0]["kernel_ms"] * 1e-3) / 1e12
     return {"value": steps * len(pairs) / dt, "unit": "pairs/s",
+            "roofline": {"bound": "alu", "achieved": alu,
+                         "peak": ALU_PEAK_TOPS, "unit": "T ops/s",
+                         "frac": alu / ALU_PEAK_TOPS},
             "pairs": len(pairs), "precision": "bf16",
             "tol_outer": BF16_TOL_OUTER,
             "accuracy_mean": float(np.mean(acc)),
@@ -217,23 +250,24 @@ def products_leg(torch, F, S, ns, nps, A, B, K, X, offs, team, steps):
         tf = flops / (np.mean(ms) * 1e-3) / 1e12
         out[name] = {"tflops": tf, "peak": MFMA_PEAK_TFLOPS[name],
                      "frac": tf / MFMA_PEAK_TFLOPS[name],
-                     "avg_launch_ms": float(np.mean(ms))}
-    out["work"] = ("8 outer steps x 1 inner pass per pair; the pass and the "
-                   "update are inside the time")
+                     "avg_launch_ms": float(np.mean(ms)),
+                     "phases": phases(infos, ns, nps, team, name)}
+    out["work"] = ("8 outer steps x 1 inner pass per pair; tflops/frac: the "
+                   "whole launch (the pass and the update inside the time); "
+                   "phases: step 3 alone, on the team's compute units")
     return out
 
 
-def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc, team):
+def warm_leg(torch, F, pairs, steps, team):
     """BF16 products from the learned warm start on the same pairs as the
     FP32 leg: the timed step is the batched warm start (X0 of every pair),
     the batched solve from it, and the uniform re-solve of any pair the
     learned start did not bring to convergence."""
-    from paper_1207_1114_amd import scores
     from paper_1207_1114_amd import warmstart as W
     try:
         params, meta = W.load_params()
     except (FileNotFoundError, RuntimeError) as e:
-        return {"skipped": str(e)}
+        return {"skipped": str(e)}, None
     b = W.pack(torch, pairs)
     n = max(max(b.ns), max(b.nps))
     S = F.Solver(n, n)
@@ -247,23 +281,67 @@ def warm_leg(torch, F, pairs, steps, fp32_value, fp32_obj, fp32_acc, team):
         infos, extra = W.solve_batched_warm(S, b, prm)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    S.close()
+    Xs = [b.x(i).cpu().numpy() for i in range(len(pairs))]
+    out = {"value": steps * len(pairs) / dt, "unit": "pairs/s",
+           "precision": "bf16", "tol_outer": W.BF16_TOL_OUTER,
+           "fallbacks": extra["fallbacks"],
+           "sharpening_beta": meta.get("beta"),
+           "accepted_on_heldout": bool(meta.get("accepted"))}
+    return out, (infos, Xs)
+
+
+def quality(F, pairs, Xs):
+    """Hungarian matching of every result: objective (trace form) and
+    accuracy against the planted correspondence."""
+    from paper_1207_1114_amd import scores
     obj, acc = [], []
-    for i, p in enumerate(pairs):
-        m, _ = F.discretize(b.x(i).cpu().numpy())
+    for p, X in zip(pairs, Xs):
+        m, _ = F.discretize(X)
         obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
         acc.append(scores.accuracy(m, p.perm))
-    value = steps * len(pairs) / dt
-    S.close()
-    return {"value": value, "unit": "pairs/s", "precision": "bf16",
-            "tol_outer": W.BF16_TOL_OUTER, "speedup_vs_fp32": value / fp32_value,
-            "objective_rel_diff_vs_fp32": float(
-                (np.mean(obj) - np.mean(fp32_obj)) / abs(np.mean(fp32_obj))),
-            "accuracy_mean": float(np.mean(acc)),
-            "accuracy_diff_vs_fp32": float(np.mean(acc) - np.mean(fp32_acc)),
-            "outer_iters_mean": float(np.mean([i["outer_iters"]
-                                               for i in infos])),
-            "fallbacks": extra["fallbacks"], "sharpening_beta": meta.get("beta"),
-            "accepted_on_heldout": bool(meta.get("accepted"))}
+    return obj, acc
+
+
+def error_vs_oracle(X, name):
+    """Upper bound of max|X - X_oracle| over every entry, against the stored
+    FP64 oracle iterate tests/golden/<name>.npz (entries above tau stored
+    exactly, the others within [-tau, tau]); None if the file is absent."""
+    path = os.path.join(ROOT, "tests", "golden", name + ".npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    flat = np.asarray(X, np.float64).ravel()
+    idx, tau = g["idx"], float(g["tau"])
+    err = float(np.abs(flat[idx] - g["val"]).max()) if idx.size else 0.0
+    rest = np.ones(flat.size, dtype=bool)
+    rest[idx] = False
+    rmax = float(np.abs(flat[rest]).max()) if rest.any() else 0.0
+    return max(err, rmax + tau) / float(g["xmax"])
+
+
+def phases(infos, ns, nps, W, prec):
+    """Mean per-pair team time in each phase (device wall-clock stamps) and
+    the products' rate within their phase: 2 n n' (n + n') flops per outer
+    step over the team's step-3 time, against the MFMA peak of the team's
+    W compute units."""
+    g = np.array([i["gemm_ms"] for i in infos])
+    pj = np.array([i["proj_ms"] for i in infos])
+    al = np.array([i["pair_ms"] for i in infos])
+    flops = np.array([2.0 * n * m * (n + m) * i["outer_iters"]
+                      for n, m, i in zip(ns, nps, infos)])
+    tf = flops / np.maximum(g * 1e-3, 1e-12) / 1e12
+    peak = MFMA_PEAK_TFLOPS[prec] * W / 256.0
+    passes = np.array([i["inner_iters_total"] for i in infos])
+    return {"team_size": W, "gemm_ms_per_pair": float(g.mean()),
+            "proj_ms_per_pair": float(pj.mean()),
+            "other_ms_per_pair": float((al - g - pj).mean()),
+            "pair_ms": float(al.mean()),
+            "proj_us_per_pass": float((pj / np.maximum(passes, 1)).mean()
+                                      * 1e3),
+            "products_tflops_in_phase": float(tf.mean()),
+            "products_frac_of_team_peak": float(tf.mean() / peak),
+            "team_peak_tflops": peak}
 
 
 def discretize_leg(torch, F, S, Xh, X, offs, n, steps):
@@ -361,6 +439,111 @@ def elementwise_reference(torch, sizes=(8192, 16384), reps=20):
     return out
 
 
+def batch_run(torch, S, ns, nps, A, B, K, X, offs, prm, steps):
+    """Warm-up plus `steps` timed batched solves; returns (pairs/s, infos of
+    the last solve, the mean launch time of the timed solves)."""
+    S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = []
+    for _ in range(steps):
+        infos = S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs,
+                                prm)
+        ms.append(infos[0]["kernel_ms"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return steps * len(ns) / dt, infos, float(np.mean(ms))
+
+
+def single_pair_leg(torch, F, p, name, steps, team=0):
+    """One pair of another configuration solved alone, FP32 (eps1 1e-6) and
+    BF16 (eps1 5e-4): pairs/s, iteration counts, error against the stored
+    FP64 oracle, matching quality."""
+    dev = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda:0")
+    S = F.Solver(p.n, p.np_)
+    A, B, K = dev(p.A), dev(p.B), dev(p.K)
+    out = {"n": p.n, "n_prime": p.np_}
+    for tag, prec, tol in (("fp32", F.FP32, 1e-6),
+                           ("bf16", F.BF16, BF16_TOL_OUTER)):
+        prm = F.default_params(lambda_=p.lam, precision=prec, tol_outer=tol,
+                               team_size=team)
+        X = torch.zeros(p.n, p.np_, device="cuda:0")
+        S.solve(A, B, K, X, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = S.solve(A, B, K, X, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Xh = X.cpu().numpy()
+        obj, acc = quality(F, [p], [Xh])
+        out[tag] = {"pairs_per_s": steps / dt, "tol_outer": tol,
+                    "outer_iters": info["outer_iters"],
+                    "inner_iters": info["inner_iters_total"],
+                    "max_abs_err_vs_fp64_oracle": error_vs_oracle(Xh, name),
+                    "objective": obj[0], "accuracy": acc[0],
+                    "gemm_ms": info["gemm_ms"], "proj_ms": info["proj_ms"]}
+    S.close()
+    return out
+
+
+def config4_leg(torch, F, steps, n=2000, count=4):
+    """Configuration 4 at its evaluation size: `count` held-out pairs at
+    n = n' = 2000, the plain method (FP32, uniform start, eps1 1e-6) against
+    BF16 products from the learned start (eps1 5e-4), both batched; pair 0
+    is compared with the stored FP64 oracle run."""
+    from paper_1207_1114_amd import synth
+    from paper_1207_1114_amd import warmstart as W
+    params, _ = W.load_params()
+    pairs = [synth.config4_pair(i, n) for i in range(count)]
+    b = W.pack(torch, pairs)
+    S = F.Solver(n, n)
+    W.solve_batched(S, b, F.default_params(lambda_=1.0))      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pinfos = W.solve_batched(S, b, F.default_params(lambda_=1.0))
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    Xp = [b.x(i).cpu().numpy() for i in range(count)]
+    S.warmstart_load(params)
+    prm = W.warm_params()
+    W.solve_batched_warm(S, b, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        winfos, extra = W.solve_batched_warm(S, b, prm)
+    torch.cuda.synchronize()
+    t_warm = (time.perf_counter() - t0) / steps
+    Xw = [b.x(i).cpu().numpy() for i in range(count)]
+    S.close()
+    op, ap = quality(F, pairs, Xp)
+    ow, aw = quality(F, pairs, Xw)
+    return {"n": n, "pairs": count,
+            "plain_fp32": {"pairs_per_s": count / t_plain,
+                           "outer_iters_mean": float(np.mean(
+                               [i["outer_iters"] for i in pinfos])),
+                           "accuracy_mean": float(np.mean(ap)),
+                           "pair0_max_abs_err_vs_fp64_oracle":
+                               error_vs_oracle(Xp[0], f"config4_n{n}_pair0"),
+                           "phases": phases(pinfos, [n] * count,
+                                            [n] * count, 64, "fp32")},
+            "bf16_warmstart": {"pairs_per_s": count / t_warm,
+                               "outer_iters_mean": float(np.mean(
+                                   [i["outer_iters"] for i in winfos])),
+                               "accuracy_mean": float(np.mean(aw)),
+                               "fallbacks": extra["fallbacks"],
+                               "pair0_max_abs_err_vs_fp64_oracle":
+                                   error_vs_oracle(Xw[0],
+                                                   f"config4_n{n}_pair0"),
+                               "phases": phases(winfos, [n] * count,
+                                                [n] * count, 64, "bf16")},
+            "speedup": t_plain / t_warm,
+            "objective_rel_diff": float((np.mean(ow) - np.mean(op))
+                                        / abs(np.mean(op))),
+            "accuracy_diff": float(np.mean(aw) - np.mean(ap))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -384,7 +567,7 @@ def main():
                           "copy_bytes_written": y.numel() * 4}), flush=True)
         return
     from paper_1207_1114_amd import fastpfp as F
-    from paper_1207_1114_amd import scores
+    from paper_1207_1114_amd import synth
 
     torch.cuda.init()
     pairs, A, B, K, X, offs = make_inputs(torch, args.pairs, args.n)
@@ -422,11 +605,7 @@ def main():
     gemm_flops = sum(i["outer_iters"] for i in infos) * 2.0 * n * n * (2 * n)
 
     Xh = X.view(args.pairs, n, n).cpu().numpy()
-    acc, obj = [], []
-    for i, p in enumerate(pairs):
-        m, _ = F.discretize(Xh[i])
-        acc.append(scores.accuracy(m, p.perm))
-        obj.append(scores.matching_objective(p.A, p.B, p.K, p.lam, m))
+    obj, acc = quality(F, pairs, list(Xh))
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -452,10 +631,14 @@ def main():
                      "work_per_launch": (f"{passes} inner passes x {n}^2 "
                                          f"entries x {OPS_PER_ENTRY_PASS} ops")},
         "gemm_tflops_in_launch": gemm_flops / (kernel_ms * 1e-3) / 1e12,
+        "phases": phases(infos, ns, nps, team, "fp32"),
         "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
         "inner_iters_mean": float(np.mean([i["inner_iters_total"]
                                            for i in infos])),
         "accuracy_mean": float(np.mean(acc)),
+        "objective_mean": float(np.mean(obj)),
+        "pair0_max_abs_err_vs_fp64_oracle": (
+            error_vs_oracle(Xh[0], "config1_pair0") if n == 1000 else None),
         "converged": int(sum(i["converged"] for i in infos)),
         "autotune": tuned,
     }
@@ -466,32 +649,64 @@ def main():
         out["projection_stream"] = stream_leg(torch, F)
         out["projection_stream"]["elementwise_add_reference"] = \
             elementwise_reference(torch)
-        # same workload with BF16 products
-        prm16 = F.default_params(lambda_=1.0, team_size=team,
-                                 precision=F.BF16, tol_outer=BF16_TOL_OUTER)
-        S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs, prm16)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            inf16 = S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X,
-                                    offs, prm16)
-        torch.cuda.synchronize()
-        dt16 = time.perf_counter() - t0
-        Xh16 = X.view(args.pairs, n, n).cpu().numpy()
-        acc16 = [scores.accuracy(F.discretize(Xh16[i])[0], p.perm)
-                 for i, p in enumerate(pairs)]
-        out["bf16"] = {"value": args.steps * args.pairs / dt16,
-                       "unit": "pairs/s", "tol_outer": BF16_TOL_OUTER,
-                       "accuracy_mean": float(np.mean(acc16)),
-                       "outer_iters_mean": float(np.mean(
-                           [i["outer_iters"] for i in inf16]))}
-        out["bf16_warmstart"] = warm_leg(torch, F, pairs, args.steps, value,
-                                         obj, acc, team)
+        # the same pairs: FP32 at the BF16 legs' eps1 (the control that
+        # separates the looser tolerance from the BF16 products), then BF16
+        legs = {}
+        for tag, prec in (("fp32_tol_5e-4", F.FP32), ("bf16", F.BF16)):
+            pr = F.default_params(lambda_=1.0, team_size=team, precision=prec,
+                                  tol_outer=BF16_TOL_OUTER)
+            v, inf, _ = batch_run(torch, S, ns, nps, A, B, K, X, offs, pr,
+                                  args.steps)
+            Xl = X.view(args.pairs, n, n).cpu().numpy()
+            ob, ac = quality(F, pairs, list(Xl))
+            legs[tag] = {"value": v, "unit": "pairs/s",
+                         "tol_outer": BF16_TOL_OUTER,
+                         "accuracy_mean": float(np.mean(ac)),
+                         "objective_rel_diff_vs_fp32": float(
+                             (np.mean(ob) - np.mean(obj)) / abs(np.mean(obj))),
+                         "outer_iters_mean": float(np.mean(
+                             [i["outer_iters"] for i in inf])),
+                         "pair0_max_abs_err_vs_fp64_oracle": (
+                             error_vs_oracle(Xl[0], "config1_pair0")
+                             if n == 1000 else None),
+                         "phases": phases(inf, ns, nps, team,
+                                          "bf16" if prec == F.BF16
+                                          else "fp32")}
+        out.update(legs)
+        warm, res = warm_leg(torch, F, pairs, args.steps, team)
+        if res is not None:
+            winf, Xw = res
+            ob, ac = quality(F, pairs, Xw)
+            warm.update({
+                "outer_iters_mean": float(np.mean([i["outer_iters"]
+                                                   for i in winf])),
+                "accuracy_mean": float(np.mean(ac)),
+                "accuracy_diff_vs_fp32": float(np.mean(ac) - np.mean(acc)),
+                "objective_rel_diff_vs_fp32": float(
+                    (np.mean(ob) - np.mean(obj)) / abs(np.mean(obj))),
+                "pair0_max_abs_err_vs_fp64_oracle": (
+                    error_vs_oracle(Xw[0], "config1_pair0")
+                    if n == 1000 else None),
+                "speedup_vs_fp32": warm["value"] / value,
+                "speedup_vs_fp32_tol_5e-4":
+                    warm["value"] / legs["fp32_tol_5e-4"]["value"],
+                # the speed-up split into its three factors (their product)
+                "factor_tolerance": legs["fp32_tol_5e-4"]["value"] / value,
+                "factor_bf16_products":
+                    legs["bf16"]["value"] / legs["fp32_tol_5e-4"]["value"],
+                "factor_learned_start": warm["value"] / legs["bf16"]["value"],
+                "phases": phases(winf, ns, nps, team, "bf16")})
+        out["bf16_warmstart"] = warm
+        out["config2"] = single_pair_leg(torch, F, synth.config2_pair(0),
+                                         "config2_pair0", args.steps)
+        out["config4"] = config4_leg(torch, F, args.steps)
         out["config3"] = ragged_batch(torch, F, args.steps)
         out["products"] = products_leg(torch, F, S, ns, nps, A, B, K, X, offs,
                                        team, args.steps)
+    S.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes)
+        out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes,
+                                           args.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FASTPFP_ABI_VERSION 5
+#define FASTPFP_ABI_VERSION 6
 
 typedef struct fastpfp_ctx* fastpfp_t;
 
@@ -118,6 +118,14 @@ typedef struct {
   double eps1_last;      /* max|X_{t+1} - X_t| of the last outer step        */
   double eps2_last;      /* max|Y_{u+1} - Y_u| of the last inner pass        */
   double kernel_ms;      /* device time of the launch that solved the pair   */
+  /* The pair's own team time by phase, from device wall-clock stamps taken
+   * by the team leader (s_memrealtime): step 3, both products with their
+   * team barriers; steps 4-7, tile load and inner loop; and everything
+   * (also the set-up and steps 8-9).  A batch runs several teams at once,
+   * so these add up per pair, not to kernel_ms. */
+  double gemm_ms;
+  double proj_ms;
+  double pair_ms;
 } fastpfp_info;
 
 /* Fills *p with the defaults: lambda 0, alpha 0.5, eps1 1e-6, eps2 1e-8,

@@ -234,7 +234,8 @@ void fill_launch(fpfp::LaunchDesc* Lp, fastpfp_t h, char* base,
 }
 
 // Copies one pair's device result into the public info struct.
-void copy_info(fastpfp_info* o, const fpfp::DevInfo& d, float ms) {
+void copy_info(fastpfp_info* o, const fpfp::DevInfo& d, float ms,
+               double wall_khz) {
   o->outer_iters = d.outer;
   o->inner_iters_total = d.inner_total;
   o->inner_iters_max = d.inner_max;
@@ -244,6 +245,9 @@ void copy_info(fastpfp_info* o, const fpfp::DevInfo& d, float ms) {
   o->eps1_last = d.eps1;
   o->eps2_last = d.eps2;
   o->kernel_ms = ms;
+  o->gemm_ms = (double)d.t_gemm / wall_khz;
+  o->proj_ms = (double)d.t_proj / wall_khz;
+  o->pair_ms = (double)d.t_all / wall_khz;
 }
 
 // Usable workgroups of one cooperative launch (a multiple of the XCD count).
@@ -415,7 +419,7 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
                 "a device-side wait exceeded its limit; results are invalid");
   fastpfp_status first = FASTPFP_OK;
   for (size_t b = 0; b < di.size(); ++b) {
-    copy_info(&infos[b], di[b], ms);
+    copy_info(&infos[b], di[b], ms, h->wall_khz);
     if (infos[b].status != 0 && first == FASTPFP_OK)
       first = (fastpfp_status)infos[b].status;
   }
@@ -496,7 +500,7 @@ fastpfp_status run_noalloc(fastpfp_t h, const PairIn& q,
   if (abort_flag != 0)
     return fail(h, FASTPFP_ERR_TIMEOUT,
                 "a device-side wait exceeded its limit; results are invalid");
-  copy_info(info, di, ms);
+  copy_info(info, di, ms, h->wall_khz);
   if (di.status != 0)
     return fail(h, (fastpfp_status)di.status,
                 "non-finite values met during the solve");
@@ -574,6 +578,10 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
   }
   // launches size their grids for the kernel that fits fewer workgroups
   h->occupancy = std::min(h->occupancy, occ_dyk);
+  int wall_khz = 0;
+  if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate,
+                            device) == hipSuccess && wall_khz > 0)
+    h->wall_khz = wall_khz;
   // the device address of this device's fixed scratch array (looked up once
   // per device, with the device current)
   void* scratch = nullptr;

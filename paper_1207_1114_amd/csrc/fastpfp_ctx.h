@@ -23,6 +23,7 @@ struct fastpfp_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int cu_count = 0;
+  double wall_khz = 100000.0;  // device wall clock (s_memrealtime) rate
   int occupancy = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> trace;

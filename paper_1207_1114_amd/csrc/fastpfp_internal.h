@@ -23,9 +23,14 @@ constexpr int kMaxTeam = kMaxTeamSide * kMaxTeamSide;
 
 enum PairMode { kModeSolve = 0, kModeProject = 1 };
 
+// Per-pair result.  t_gemm / t_proj / t_all: the team's wall-clock ticks
+// (s_memrealtime, constant rate) spent in step 3 (both products and their
+// team barriers), in steps 4-7 (tile load and inner loop), and on the whole
+// pair, as seen by the team leader.
 struct DevInfo {
   int outer, inner_total, inner_max, inner_capped, converged, status;
   float eps1, eps2;
+  unsigned long long t_gemm, t_proj, t_all;
 };
 
 // One matching problem as the persistent kernel sees it.

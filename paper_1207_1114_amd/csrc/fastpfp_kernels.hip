@@ -698,8 +698,15 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
             r += xn;
             cs[b] += xn;
           } else {
-            dd = fmaxf((y + av_a) + bv[b], 0.f);
-            dm = fmaxf(dm, fabsf(dd - y));
+            // max(y + t, 0) = y + max(t, -y) with t = a_i + b_j: the change
+            // of the entry comes out directly, and the new entry is exactly
+            // 0 where the clamp acts.  max(t, -y) as the median of
+            // (t, -y, FLT_MAX): one instruction with -y as a source modifier
+            // (an infinite t, from non-finite sums, is caught by the sums)
+            const float del = __builtin_amdgcn_fmed3f(av_a + bv[b], -y,
+                                                      3.402823466e38f);
+            dd = y + del;
+            dm = fmaxf(dm, fabsf(del));
             r += dd;
             cs[b] += dd;
           }
@@ -809,7 +816,8 @@ fastpfp_persistent(LaunchDesc L) {
     const int n = pd.n, np = pd.np, N = pd.N;
     float* const Y = pd.Y ? pd.Y : Yws;
     const TileGeom g = tile_geom(tm, N);
-    DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f};
+    DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0ull, 0ull, 0ull};
+    const unsigned long long t_pair = wall_clock64();
     float Yr[kRegRows][kCB];
 
     if (pd.mode == kModeProject) {
@@ -818,6 +826,7 @@ fastpfp_persistent(LaunchDesc L) {
       if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
                             &numeric, pr, pc))
         return;
+      info.t_proj = wall_clock64() - t_pair;
       store_tile(Yr, sh, Y, N, g, pr, pc);
       info.status = numeric ? 5 : 0;
     } else {
@@ -879,6 +888,7 @@ fastpfp_persistent(LaunchDesc L) {
       for (int t = 1; t <= pd.max_outer; ++t) {
         // ---- step 3: Y[:n,:np] = A X B + lam K.  FP32: T^T = X^T A (np x n)
         // then T B; BF16: T = A X from the shadows, then T B.
+        const unsigned long long t_step = wall_clock64();
         {
           const float lam = pd.lam;
           const float* const Kp = pd.K;
@@ -916,12 +926,15 @@ fastpfp_persistent(LaunchDesc L) {
           }
         }
         if (!team_sync_bulk(tm, sh)) return;
+        const unsigned long long t_gemm_end = wall_clock64();
+        info.t_gemm += t_gemm_end - t_step;
         // ---- steps 4-7
         load_tile(Yr, sh, Y, N, g, pr, pc);
         bool numeric = false;
         if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
                               &numeric, pr, pc))
           return;
+        info.t_proj += wall_clock64() - t_gemm_end;
         if (numeric) {
           info.status = 5;
           break;
@@ -1050,6 +1063,7 @@ fastpfp_persistent(LaunchDesc L) {
         }
       }
     }
+    info.t_all = wall_clock64() - t_pair;
     if (tm.rank == 0 && tid == 0) *pd.info = info;
   }
 }

@@ -115,6 +115,8 @@ extern "C" fastpfp_status fastpfp_project_stream(fastpfp_t h, int N, float* Y,
     info->converged = cnt[0] == 1 ? 1 : 0;
     info->eps2_last = sc[1];
     info->kernel_ms = ms;
+    info->proj_ms = ms;
+    info->pair_ms = ms;
     info->status = cnt[0] == 2 ? FASTPFP_ERR_NUMERIC : FASTPFP_OK;
   }
   if (cnt[0] == 2)

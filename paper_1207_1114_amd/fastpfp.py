@@ -23,7 +23,7 @@ INIT_UNIFORM, INIT_USER = 0, 1
 HUNGARIAN, GREEDY = 0, 1
 ALTERNATING, DYKSTRA = 0, 1
 METHOD_FASTPFP, METHOD_PG = 0, 1
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape out of range",
           3: "HIP runtime error", 4: "out of device memory",
@@ -62,7 +62,9 @@ class Info(ctypes.Structure):
                 ("inner_iters_max", ctypes.c_int),
                 ("inner_capped", ctypes.c_int), ("converged", ctypes.c_int),
                 ("status", ctypes.c_int), ("eps1_last", ctypes.c_double),
-                ("eps2_last", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("eps2_last", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("proj_ms", ctypes.c_double),
+                ("pair_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

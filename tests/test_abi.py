@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(F):
     for nm in names:
         assert hasattr(lib, nm), nm
     assert set(F.EXPORTS) <= set(names)
-    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 5
+    assert lib.fastpfp_abi_version() == F.ABI_VERSION == 6
 
 
 def test_status_strings_and_defaults(F):

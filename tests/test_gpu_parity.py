@@ -16,6 +16,7 @@ import pytest
 
 from oracle import fastpfp_oracle as O
 from paper_1207_1114_amd import synth
+from parity_util import BF16_X_ERR, assert_full_parity, full_error
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -143,10 +144,8 @@ def test_solve_config1_full_size_against_stored_oracle(env):
     k = min(len(tr), len(ref_tr))
     assert np.all(np.abs(tr[:k] - ref_tr[:k]) <= 1e-5 + 1e-3 * ref_tr[:k])
     assert abs(info["outer_iters"] - int(g["outer"])) <= 1
-    got = X[g["rows"], g["cols"]]
-    assert np.abs(got - g["xs"]).max() <= 1e-4 * float(g["xmax"])
+    assert_full_parity(X, g)
     np.testing.assert_array_equal(O.hungarian_discretize(X), g["match"])
-    # unsampled entries: row / column sums of the whole iterate
     np.testing.assert_allclose(X.sum(1), g["xsum_rows"], atol=1e-3)
     np.testing.assert_allclose(X.sum(0), g["xsum_cols"], atol=1e-3)
 
@@ -236,6 +235,39 @@ def test_batched_equals_single_solves(env):
         assert inf["inner_iters_total"] == info["inner_iters_total"]
 
 
+def test_batch_with_a_nan_pair_leaves_the_others_intact(env):
+    """One pair of a config-3 batch holds a NaN in A: that pair reports
+    NUMERIC, the call returns NUMERIC, and every other pair's iterate and
+    counts equal its own single solve bitwise."""
+    torch, F, S = env
+    pairs = [synth.config3_pair(400 + i) for i in range(6)]
+    bad = 2
+    A = pairs[bad].A.copy()
+    A[5, 7] = A[7, 5] = np.nan
+    pairs[bad] = synth.GraphPair(A, pairs[bad].B, pairs[bad].K,
+                                 pairs[bad].lam, pairs[bad].perm)
+    prm = F.default_params(lambda_=1.0, max_outer=6, max_inner=150,
+                           precision=F.BF16, tol_outer=5e-4)
+    bufs, offs = pack(pairs)
+    d = {k: dev(torch, v).view(-1, 1) for k, v in bufs.items()}
+    with pytest.raises(F.FastPFPError) as e:
+        S.solve_batched([p.n for p in pairs], [p.np_ for p in pairs],
+                        d["A"], offs["A"], d["B"], offs["B"], d["K"],
+                        offs["K"], d["X"], offs["X"], prm)
+    assert e.value.status == 5
+    infos = e.value.infos
+    assert [i["status"] for i in infos] == [5 if k == bad else 0
+                                           for k in range(len(pairs))]
+    Xall = d["X"].cpu().numpy().ravel()
+    for k, (p, o, inf) in enumerate(zip(pairs, offs["X"], infos)):
+        if k == bad:
+            continue
+        Xb = Xall[o:o + p.n * p.np_].reshape(p.n, p.np_)
+        Xs, info, _ = gpu_solve(env, p, prm=prm)
+        np.testing.assert_array_equal(Xb, Xs)
+        assert inf["outer_iters"] == info["outer_iters"] >= 2
+
+
 # ------------------------------------------------------ BF16 products
 @pytest.mark.parametrize("n,m", [(70, 90), (90, 70)])
 def test_bf16_products_match_recipe_oracle(env, n, m):
@@ -260,29 +292,33 @@ def test_bf16_products_match_recipe_oracle(env, n, m):
 
 
 def test_bf16_and_fp32_config2_full_size(env):
-    """Config 2 (n = 1000, n' = 1200, 200 outliers): error of the FP32 and
-    BF16 forms against the stored FP64 oracle; BF16 keeps the FP32 run's
-    matching accuracy within 0.5 pp and its objective within 1e-3."""
+    """Config 2 (n = 1000, n' = 1200, 200 outliers): every entry of the FP32
+    form within 1e-4 max X of the stored FP64 oracle with the same matching;
+    the BF16 form's error against it bounded and reported, and BF16 keeps
+    the FP32 run's matching accuracy within 0.5 pp and its objective within
+    1e-3."""
     torch, F, S = env
     g = np.load(os.path.join(GOLD, "config2_pair0.npz"))
     p = synth.config2_pair(0)
     res = {}
     for name, prec in (("fp32", F.FP32), ("bf16", F.BF16)):
-        # BF16 stops at 5e-4: its eps1 wanders on a plateau below ~3e-4
         tol = 5e-4 if prec == F.BF16 else 1e-6
         X, info, _ = gpu_solve(env, p, lambda_=p.lam, precision=prec,
                                tol_outer=tol)
         m = O.hungarian_discretize(X)
         res[name] = dict(
-            err=float(np.abs(X[g["rows"], g["cols"]] - g["xs"]).max()),
+            X=X, err=full_error(X, g)[2], match=m,
             acc=O.accuracy(m, p.perm), obj=O.objective(p.A, p.B, p.K, p.lam, m),
             outer=info["outer_iters"])
     print(f"config2 oracle: acc {float(g['accuracy']):.4f} "
           f"obj {float(g['objective']):.6e} outer {int(g['outer'])}")
     for k, v in res.items():
-        print(f"config2 {k}: max|X - X_fp64| on samples {v['err']:.3e}, "
-              f"acc {v['acc']:.4f}, obj {v['obj']:.6e}, outer {v['outer']}")
-    assert res["fp32"]["err"] <= 1e-4 * float(g["xmax"])
+        print(f"config2 {k}: max|X - X_fp64| over every entry <= "
+              f"{v['err']:.3e}, acc {v['acc']:.4f}, obj {v['obj']:.6e}, "
+              f"outer {v['outer']}")
+    assert_full_parity(res["fp32"]["X"], g)
+    np.testing.assert_array_equal(res["fp32"]["match"], g["match"])
+    assert res["bf16"]["err"] <= BF16_X_ERR * float(g["xmax"])
     assert res["bf16"]["acc"] >= res["fp32"]["acc"] - 0.005
     assert abs(res["bf16"]["obj"] - res["fp32"]["obj"]) <= \
         1e-3 * abs(res["fp32"]["obj"])
