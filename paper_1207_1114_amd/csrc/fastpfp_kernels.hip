@@ -52,11 +52,17 @@ __device__ __forceinline__ float unpack(uint64_t w) {
 __device__ __forceinline__ unsigned tag_of(uint64_t w) {
   return (unsigned)(w >> 32);
 }
+// The exchange words live in global memory.  Saying so lets the compiler use
+// global (not flat) stores and loads: a flat access may also reach LDS, and
+// the compiler then made every flat store of a post wait for all earlier
+// memory operations, so a workgroup's posts left one at a time.
+typedef __attribute__((address_space(1))) uint64_t gword;
 __device__ __forceinline__ void put_word(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((gword*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t get_word(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const gword*)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-workgroup view of its team.
@@ -523,18 +529,37 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
     uint64_t* rowp = buf;                        // [TC][NPR]
     uint64_t* colp = buf + tm.TC * NPR;          // [TR][NPC]
     uint64_t* scal = buf + (tm.par_words - (long long)tm.W * kScal);
-    if (t < g.h) put_word(rowp + tm.tc * NPR + g.r0 + t, pack(seq, rpart));
-    if (t < g.w) put_word(colp + tm.tr * NPC + g.c0 + t, pack(seq, cpart));
-    __syncthreads();
-    if (tid == 0) {
+    __syncthreads();  // the four waves' tile partials in sh.dtile
+    // Every address and word of this thread's posts is formed first and the
+    // stores then issue back to back: the memory counter also counts stores,
+    // so a spill reload between two posts of a thread would hold the second
+    // until the first is acknowledged.
+    uint64_t* ra = rowp + tm.tc * NPR + g.r0 + t;
+    uint64_t* ca = colp + tm.tr * NPC + g.c0 + t;
+    uint64_t* sa = scal + tm.rank * kScal;
+    int post_r = t < g.h, post_c = t < g.w, post_s = tid == 0;
+    uint64_t wr = pack(seq, rpart), wc = pack(seq, cpart);
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    if (post_s) {
       const double ttot = ((sh.dtile[0] + sh.dtile[1]) + sh.dtile[2]) +
                           sh.dtile[3];
       const float hi = (float)ttot;
       const float lo = (float)(ttot - (double)hi);
-      put_word(scal + tm.rank * kScal + 0, pack(seq, hi));
-      put_word(scal + tm.rank * kScal + 1, pack(seq, lo));
-      put_word(scal + tm.rank * kScal + 2, pack(seq, dmw));
-      put_word(scal + tm.rank * kScal + 3, pack(seq, 0.f));
+      w0 = pack(seq, hi);
+      w1 = pack(seq, lo);
+      w2 = pack(seq, dmw);
+      w3 = pack(seq, 0.f);
+    }
+    asm volatile("" : "+v"(ra), "+v"(ca), "+v"(sa), "+v"(post_r),
+                 "+v"(post_c), "+v"(post_s), "+v"(wr), "+v"(wc), "+v"(w0),
+                 "+v"(w1), "+v"(w2), "+v"(w3));
+    if (post_r) put_word(ra, wr);
+    if (post_c) put_word(ca, wc);
+    if (post_s) {
+      put_word(sa + 0, w0);
+      put_word(sa + 1, w1);
+      put_word(sa + 2, w2);
+      put_word(sa + 3, w3);
     }
     __builtin_amdgcn_s_sleep(kPostSleep);
     // this thread's runs: TC row partials of row t and TR column partials of
