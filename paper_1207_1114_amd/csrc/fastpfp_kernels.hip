@@ -65,6 +65,15 @@ __device__ __forceinline__ uint64_t get_word(const uint64_t* p) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Global-memory view of a device pointer.  Every matrix the kernel reads or
+// writes is in device memory; through generic pointers those accesses become
+// flat instructions, which also count against the LDS counter, so a wait for
+// an LDS read (e.g. a product's operand tile) would wait for them as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Per-workgroup view of its team.
 struct Team {
   int team, rank, W, TR, TC, tr, tc;
@@ -112,13 +121,13 @@ __device__ __forceinline__ int opaque(int x) {
 }
 
 __device__ __forceinline__ bool timed_out(const Team& tm, long long& t0) {
-  if (__hip_atomic_load(tm.abort_flag, __ATOMIC_RELAXED,
+  if (__hip_atomic_load(gbl(tm.abort_flag), __ATOMIC_RELAXED,
                         __HIP_MEMORY_SCOPE_AGENT) != 0u)
     return true;
   const long long now = (long long)wall_clock64();
   if (t0 == 0) t0 = now;
   if (now - t0 > tm.timeout) {
-    __hip_atomic_store(tm.abort_flag, 1u, __ATOMIC_RELAXED,
+    __hip_atomic_store(gbl(tm.abort_flag), 1u, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
     return true;
   }
@@ -222,13 +231,17 @@ __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
 // in kGT x kGT output tiles dealt round-robin over the team.  Each wave owns
 // a 64 x 64 quarter as 2 x 2 blocks of v_mfma_f32_32x32x2_f32; operands are
 // staged through LDS kGK k-rows at a time, the next step's operands being
-// loaded into registers while the current one computes.  epi(m, c, value)
-// stores one result.
-template <class Epi>
+// loaded into registers while the current one computes.  The epilogue takes
+// each 32 x 32 block in three sweeps, so that its loads are in flight
+// together and no store waits on a load: pre(m, c) loads what a result needs
+// (it is also called at positions outside the result, m >= M or c >= Nc,
+// where it must stay inside its operands), fin(value, pre) forms the value to
+// store, and put(m, c, v) stores it (inside the result only).
+template <class Pre, class Fin, class Put>
 __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
                               const float* __restrict__ Q, int ldq, int M,
                               int Nc, int Kd, const Team& tm, Shared& sh,
-                              Epi epi) {
+                              Pre pre, Fin fin, Put put) {
   constexpr int kPer = kGK * kGT / kThreads;  // operand elements per thread
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -246,26 +259,17 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
     // element e of this thread's share: k-row (tid + 256 e) / kGT, col % kGT
     const int mm = tid & (kGT - 1), kb = tid / kGT;
     const bool pm = m0 + mm < M, qm = n0 + mm < Nc;
+    // Loads are unconditional, from addresses clamped into the operands, and
+    // values outside them are zeroed when staged: one code path, so the
+    // prefetch is not waited for where two paths would merge.
+    const int pmc = min(m0 + mm, M - 1), qmc = min(n0 + mm, Nc - 1);
     float pa[kPer], qa[kPer];
-    // a tile inside both operands, at a k-step inside Kd, needs no bounds
-    // checks: its loads are then unconditional and issue together
-    const bool tile_in = m0 + kGT <= M && n0 + kGT <= Nc;
     auto fetch = [&](int k0) {
-      if (tile_in && k0 + kGK <= Kd) {
-#pragma unroll
-        for (int e = 0; e < kPer; ++e) {
-          const int kg = k0 + kb + e * (kThreads / kGT);
-          pa[e] = P[(long long)kg * ldp + m0 + mm];
-          qa[e] = Q[(long long)kg * ldq + n0 + mm];
-        }
-        return;
-      }
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int kg = k0 + kb + e * (kThreads / kGT);
-        const bool kin = kg < Kd;
-        pa[e] = (kin && pm) ? P[(long long)kg * ldp + m0 + mm] : 0.f;
-        qa[e] = (kin && qm) ? Q[(long long)kg * ldq + n0 + mm] : 0.f;
+        const int kg = min(k0 + kb + e * (kThreads / kGT), Kd - 1);
+        pa[e] = gbl(P)[(long long)kg * ldp + pmc];
+        qa[e] = gbl(Q)[(long long)kg * ldq + qmc];
       }
     };
     fetch(0);
@@ -273,8 +277,9 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        sh.t.g.lp[kb + e * (kThreads / kGT)][mm] = pa[e];
-        sh.t.g.lq[kb + e * (kThreads / kGT)][mm] = qa[e];
+        const bool kin = k0 + kb + e * (kThreads / kGT) < Kd;
+        sh.t.g.lp[kb + e * (kThreads / kGT)][mm] = (kin && pm) ? pa[e] : 0.f;
+        sh.t.g.lq[kb + e * (kThreads / kGT)][mm] = (kin && qm) ? qa[e] : 0.f;
       }
       __syncthreads();
       if (k0 + kGK < Kd) fetch(k0 + kGK);
@@ -306,11 +311,20 @@ __device__ void team_gemm_f32(const float* __restrict__ P, int ldp,
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int cc = n0 + wc * 64 + 32 * j + (lane & 31);
+        float2 ad[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          ad[v] = pre(m0 + wr * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) +
+                          (v & 3),
+                      cc);
+        float yv[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) yv[v] = fin(acc[i][j][v], ad[v]);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const int mr = m0 + wr * 64 + 32 * i + 8 * (v >> 2) +
                          4 * (lane >> 5) + (v & 3);
-          if (mr < M && cc < Nc) epi(mr, cc, acc[i][j][v]);
+          if (mr < M && cc < Nc) put(mr, cc, yv[v]);
         }
       }
   }
@@ -329,14 +343,15 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // C[m][c] = sum_k P[m*ld + k] * Q[c*ld + k] with bfloat16 operands and
 // float32 accumulation (v_mfma_f32_32x32x16_bf16), over the zero-padded
 // shadows: Mt, Nt multiples of kGT, Kd a multiple of kBK; every tile is
-// computed and epi(m, c, value) receives all Mt x Nt results.  Each wave
-// owns a 64 x 64 quarter of a kGT x kGT tile; operands are staged through
-// LDS kBK k at a time with the next step prefetched into registers.
-template <class Epi>
+// computed and pre / fin / put (as in team_gemm_f32) see all Mt x Nt
+// results.  Each wave owns a 64 x 64 quarter of a kGT x kGT tile; operands
+// are staged through LDS kBK k at a time with the next step prefetched into
+// registers.
+template <class Pre, class Fin, class Put>
 __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
                                const uint16_t* __restrict__ Q, int ld, int Mt,
                                int Nt, int Kd, const Team& tm, Shared& sh,
-                               Epi epi) {
+                               Pre pre, Fin fin, Put put) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int tiles_n = Nt / kGT, ntiles = (Mt / kGT) * tiles_n;
@@ -351,8 +366,8 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-    const u32x4* prow = (const u32x4*)(P + (long long)(m0 + sr) * ld + sk);
-    const u32x4* qrow = (const u32x4*)(Q + (long long)(n0 + sr) * ld + sk);
+    const auto prow = gbl((const u32x4*)(P + (long long)(m0 + sr) * ld + sk));
+    const auto qrow = gbl((const u32x4*)(Q + (long long)(n0 + sr) * ld + sk));
     u32x4 pa0 = prow[0], pa1 = prow[1], qa0 = qrow[0], qa1 = qrow[1];
     for (int k0 = 0; k0 < Kd; k0 += kBK) {
       __syncthreads();
@@ -387,12 +402,19 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int cc = n0 + wc * 64 + 32 * j + (lane & 31);
+        float2 ad[16];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int mr = m0 + wr * 64 + 32 * i + 8 * (v >> 2) +
-                         4 * (lane >> 5) + (v & 3);
-          epi(mr, cc, acc[i][j][v]);
-        }
+        for (int v = 0; v < 16; ++v)
+          ad[v] = pre(m0 + wr * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) +
+                          (v & 3),
+                      cc);
+        float yv[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) yv[v] = fin(acc[i][j][v], ad[v]);
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          put(m0 + wr * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3),
+              cc, yv[v]);
       }
   }
 }
@@ -465,8 +487,11 @@ __device__ __forceinline__ float row16_sum(float v) {
 
 // Cycles to sleep (in units of 64 clocks) between posting an exchange and
 // the first load of it: about one store-to-visibility latency, so the first
-// loads usually find the data instead of polling.
-constexpr int kPostSleep = 8;
+// loads usually find the data instead of polling.  Measured with 16 teams of
+// 16 at n = 1000 (in-solve pass time): 3 -> 8.08 us, 8 -> 8.06, 16 -> 7.53,
+// 24 -> 7.71, 32 -> 7.92, 48 -> 8.34; shorter sleeps add polling traffic that
+// slows every team.
+constexpr int kPostSleep = 16;
 
 // One team exchange of a pass.  In: each thread's row partials rs[a] (over
 // its kCB columns), column partials cs[b] (over its kRA rows) and its
@@ -625,7 +650,7 @@ __device__ __forceinline__ void load_tile(float (&Yr)[kRegRows][kCB],
 #pragma unroll
   for (int a = 0; a < kRA; ++a) {
     const int li = pr + 16 * a;
-    const float* rp = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
+    const auto rp = gbl(Y + (long long)(g.r0 + li) * N + g.c0 + pc);
 #pragma unroll
     for (int b = 0; b < kCB; ++b) {
       const float v = (li < hv && pc + 16 * b < wv) ? rp[16 * b] : 0.f;
@@ -643,7 +668,7 @@ __device__ __forceinline__ void store_tile(const float (&Yr)[kRegRows][kCB],
 #pragma unroll
   for (int a = 0; a < kRA; ++a) {
     const int li = pr + 16 * a;
-    float* rp = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
+    const auto rp = gbl(Y + (long long)(g.r0 + li) * N + g.c0 + pc);
 #pragma unroll
     for (int b = 0; b < kCB; ++b)
       if (li < hv && pc + 16 * b < wv)
@@ -870,8 +895,8 @@ fastpfp_persistent(LaunchDesc L) {
         for (int a = 0; a < kRA; ++a) {
           const int li = pr + 16 * a;
           if (li < hv) {
-            float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
-            float* yrow = Y + (long long)(g.r0 + li) * N + g.c0 + pc;
+            const auto xrow = gbl(X + (long long)(g.r0 + li) * ldx + g.c0 + pc);
+            const auto yrow = gbl(Y + (long long)(g.r0 + li) * N + g.c0 + pc);
 #pragma unroll
             for (int bb = 0; bb < kCB; ++bb) {
               const int lj = pc + 16 * bb;
@@ -902,10 +927,13 @@ fastpfp_persistent(LaunchDesc L) {
         for (long long e = (long long)tm.rank * kThreads + tid; e < Np2;
              e += (long long)tm.W * kThreads) {
           const int r = (int)(e / Np), c = (int)(e % Np);
-          Ah[e] = (r < n && c < n) ? f2bf(pd.A[(long long)r * pd.lda + c]) : 0;
-          Bh[e] = (r < np && c < np) ? f2bf(pd.B[(long long)r * pd.ldb + c]) : 0;
-          Xh[e] = (r < np && c < n)
-                      ? f2bf(user ? X[(long long)c * ldx + r] : c0) : 0;
+          gbl(Ah)[e] =
+              (r < n && c < n) ? f2bf(gbl(pd.A)[(long long)r * pd.lda + c]) : 0;
+          gbl(Bh)[e] =
+              (r < np && c < np) ? f2bf(gbl(pd.B)[(long long)r * pd.ldb + c]) : 0;
+          gbl(Xh)[e] = (r < np && c < n)
+                           ? f2bf(user ? gbl(X)[(long long)c * ldx + r] : c0)
+                           : 0;
         }
       }
       if (!team_sync_bulk(tm, sh)) return;
@@ -915,39 +943,54 @@ fastpfp_persistent(LaunchDesc L) {
         // then T B; BF16: T = A X from the shadows, then T B.
         const unsigned long long t_step = wall_clock64();
         {
-          const float lam = pd.lam;
-          const float* const Kp = pd.K;
-          const int ldk = pd.ldk, NN = N, nn = n, npp = np;
+          const int NN = N, nn = n, npp = np;
           float* const Yw = Y;
-          // Projected Gradient (eq. pg): Y = X + step * gradient
-          const float step = pd.pg_step;
-          const float* const Xp = step != 0.f ? X : nullptr;
-          const int ldxp = ldx;
-          auto out = [=](int m, int c, float val) {
-            if (m < nn && c < npp) {
-              float yv = val;
-              if (Kp) yv += lam * Kp[(long long)m * ldk + c];
-              if (Xp) yv = Xp[(long long)m * ldxp + c] + step * yv;
-              Yw[(long long)m * NN + c] = yv;
-            }
+          // Y = (step * (A X B + lam K) + w X): w = 0, step = 1 for FastPFP;
+          // w = 1 and the step of eq. (pg) for Projected Gradient.  The
+          // epilogue has no branches on these (inside the out-of-line product
+          // they are per-lane values, and a branch there made every store
+          // wait): without K its loads read X with lam = 0, and a FastPFP
+          // pair reads the K source a second time with w = 0.
+          const bool pg = pd.pg_step != 0.f;
+          const float* const Ks = pd.K ? pd.K : X;
+          const int ldks = pd.K ? pd.ldk : ldx;
+          const float lam = pd.K ? pd.lam : 0.f;
+          const float* const Xs = pg ? X : Ks;
+          const int ldxs = pg ? ldx : ldks;
+          const float wx = pg ? 1.f : 0.f, step = pg ? pd.pg_step : 1.f;
+          // K and X loaded for a whole block before its stores, from
+          // positions clamped into the n x n' block (results outside it are
+          // not stored), with no arithmetic on them until all are issued
+          auto out_pre = [=](int m, int c) {
+            const long long mc = min(m, nn - 1), cl = min(c, npp - 1);
+            return make_float2(gbl(Ks)[mc * ldks + cl], gbl(Xs)[mc * ldxs + cl]);
           };
+          auto out_fin = [=](float val, float2 ad) {
+            return wx * ad.y + step * (val + lam * ad.x);
+          };
+          auto out = [=](int m, int c, float yv) {
+            if (m < nn && c < npp) gbl(Yw)[(long long)m * NN + c] = yv;
+          };
+          auto no_pre = [](int, int) { return make_float2(0.f, 0.f); };
+          auto same = [](float val, float2) { return val; };
           if (bf) {
             const int ld = Np;
             team_gemm_bf16(Ah, Xh, Np, Mt, Nt, (n + kBK - 1) / kBK * kBK, tm,
-                           sh, [=](int m, int c, float val) {
-                             Th[(long long)m * ld + c] = f2bf(val);
+                           sh, no_pre, same, [=](int m, int c, float val) {
+                             gbl(Th)[(long long)m * ld + c] = f2bf(val);
                            });
             if (!team_sync_bulk(tm, sh)) return;
             team_gemm_bf16(Th, Bh, Np, Mt, Nt, (np + kBK - 1) / kBK * kBK, tm,
-                           sh, out);
+                           sh, out_pre, out_fin, out);
           } else {
             float* const Tw = Tt;
-            team_gemm_f32(X, ldx, pd.A, pd.lda, np, n, n, tm, sh,
+            team_gemm_f32(X, ldx, pd.A, pd.lda, np, n, n, tm, sh, no_pre, same,
                           [=](int m, int c, float val) {
-                            Tw[(long long)m * nn + c] = val;
+                            gbl(Tw)[(long long)m * nn + c] = val;
                           });
             if (!team_sync_bulk(tm, sh)) return;
-            team_gemm_f32(Tt, n, pd.B, pd.ldb, n, np, np, tm, sh, out);
+            team_gemm_f32(Tt, n, pd.B, pd.ldb, n, np, np, tm, sh, out_pre,
+                          out_fin, out);
           }
         }
         if (!team_sync_bulk(tm, sh)) return;
@@ -976,7 +1019,7 @@ fastpfp_persistent(LaunchDesc L) {
           float xa[kCB], xb[kCB];
           auto load_xrow = [&](int a, float (&dst)[kCB]) {
             const int li = pr + 16 * a;
-            const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+            const auto xrow = gbl(X + (long long)(g.r0 + li) * ldx + g.c0 + pc);
 #pragma unroll
             for (int bb = 0; bb < kCB; ++bb)
               dst[bb] = (li < rmax && pc + 16 * bb < cmax) ? xrow[16 * bb]
@@ -1024,7 +1067,7 @@ fastpfp_persistent(LaunchDesc L) {
           float xa[kCB], xb[kCB];
           auto load_xrow = [&](int a, float (&dst)[kCB]) {
             const int li = pr + 16 * a;
-            const float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+            const auto xrow = gbl(X + (long long)(g.r0 + li) * ldx + g.c0 + pc);
 #pragma unroll
             for (int bb = 0; bb < kCB; ++bb)
               dst[bb] = (li < rmax && pc + 16 * bb < cmax) ? xrow[16 * bb]
@@ -1055,7 +1098,7 @@ fastpfp_persistent(LaunchDesc L) {
           for (int a = 0; a < kRA; ++a) {
             const int li = pr + 16 * a;
             if (li < rmax) {
-              float* xrow = X + (long long)(g.r0 + li) * ldx + g.c0 + pc;
+              const auto xrow = gbl(X + (long long)(g.r0 + li) * ldx + g.c0 + pc);
 #pragma unroll
               for (int bb = 0; bb < kCB; ++bb)
                 if (pc + 16 * bb < cmax) {
@@ -1063,7 +1106,7 @@ fastpfp_persistent(LaunchDesc L) {
                   const float xv = norm ? xn / m : xn;
                   xrow[16 * bb] = xv;
                   if (bf)
-                    Xh[(long long)(g.c0 + pc + 16 * bb) * Np + g.r0 + li] =
+                    gbl(Xh)[(long long)(g.c0 + pc + 16 * bb) * Np + g.r0 + li] =
                         f2bf(xv);
                 }
             }
