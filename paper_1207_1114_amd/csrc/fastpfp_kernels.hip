@@ -27,8 +27,8 @@
 // tile row sums, column sums, tile totals and max|dY|: every 64-bit word
 // carries the exchange's sequence number in its high half, so the data itself
 // is the signal and no separate barrier or fence is needed.  Bulk data (T, Y,
-// X) crosses workgroups through global memory with agent-scope
-// release/acquire fences around an exchange.
+// X) crosses workgroups through global memory with release/acquire fences
+// around an exchange (L2-level when the team sits on one XCD).
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -82,11 +82,16 @@ struct Team {
   unsigned seq;        // sequence number of the last exchange
   unsigned* abort_flag;
   long long timeout;   // wall clock ticks one wait may last
+  bool one_xcd;        // every workgroup of the team runs on the same XCD
 };
 
 constexpr int kGT = 128;  // GEMM output tile (kGT x kGT per workgroup)
 constexpr int kGK = 16;   // GEMM k-rows staged per step
 constexpr int kBK = 32;   // BF16 GEMM k per step
+#ifndef FPFP_BF16_PREFETCH
+#define FPFP_BF16_PREFETCH 2
+#endif
+constexpr int kBfPrefetch = FPFP_BF16_PREFETCH;  // BF16 k-steps fetched ahead
 
 struct Shared {
   union {
@@ -216,13 +221,41 @@ __device__ bool xchg_scalars(Team& tm, Shared& sh, const float (&mine)[kScal]) {
   return __syncthreads_or(!ok) == 0;
 }
 
+// Fences around handing bulk data (T, Y, X, written with ordinary stores)
+// between the workgroups of a team.  A team whose workgroups all run on one
+// XCD shares that die's L2: a store is visible to the team once it has
+// reached L2 (its memory counter is zero), and a reader only has to drop its
+// own CU's L1 lines -- the same steps the compiler uses for a workgroup split
+// over CUs.  A team spread over several XCDs needs the agent-scope fences,
+// which write back and invalidate the whole L2 (also evicting the operands of
+// every other team on the die).
+__device__ __forceinline__ void bulk_release(const Team& tm) {
+  if (tm.one_xcd) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  }
+}
+__device__ __forceinline__ void bulk_acquire(const Team& tm) {
+  if (tm.one_xcd)
+    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Index of the XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // XCC_ID[3:0]
+}
+
 // Team barrier for bulk data written with ordinary stores: release fence,
 // scalar exchange, acquire fence.
 __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  bulk_release(tm);
   const float z[kScal] = {0.f, 0.f, 0.f, 0.f};
   const bool ok = xchg_scalars(tm, sh, z);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  bulk_acquire(tm);
   return ok;
 }
 
@@ -354,10 +387,18 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
                                Pre pre, Fin fin, Put put) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int tiles_n = Nt / kGT, ntiles = (Mt / kGT) * tiles_n;
+  // Arguments of an out-of-line function arrive in vector registers; the
+  // sizes and the rank are the same in every lane, and saying so keeps the
+  // loop tests scalar.
+  ld = __builtin_amdgcn_readfirstlane(ld);
+  const int tiles_n = __builtin_amdgcn_readfirstlane(Nt) / kGT;
+  const int ntiles = (__builtin_amdgcn_readfirstlane(Mt) / kGT) * tiles_n;
+  const int nsteps = __builtin_amdgcn_readfirstlane(Kd) / kBK;
+  const int rank = __builtin_amdgcn_readfirstlane(tm.rank);
+  const int W = __builtin_amdgcn_readfirstlane(tm.W);
   // this thread stages row tid/2, k-half (tid%2)*16 of both operand tiles
   const int sr = tid >> 1, sk = (tid & 1) * 16;
-  for (int q = tm.rank; q < ntiles; q += tm.W) {
+  for (int q = rank; q < ntiles; q += W) {
     const int m0 = (q / tiles_n) * kGT, n0 = (q % tiles_n) * kGT;
     floatx16 acc[2][2];
 #pragma unroll
@@ -368,32 +409,57 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
     const auto prow = gbl((const u32x4*)(P + (long long)(m0 + sr) * ld + sk));
     const auto qrow = gbl((const u32x4*)(Q + (long long)(n0 + sr) * ld + sk));
-    u32x4 pa0 = prow[0], pa1 = prow[1], qa0 = qrow[0], qa1 = qrow[1];
-    for (int k0 = 0; k0 < Kd; k0 += kBK) {
-      __syncthreads();
-      *(u32x4*)&sh.t.h.lp[sr][sk] = pa0;
-      *(u32x4*)&sh.t.h.lp[sr][sk + 8] = pa1;
-      *(u32x4*)&sh.t.h.lq[sr][sk] = qa0;
-      *(u32x4*)&sh.t.h.lq[sr][sk + 8] = qa1;
-      __syncthreads();
-      if (k0 + kBK < Kd) {
-        const int step = (k0 + kBK) / 8;  // in 16-byte units
-        pa0 = prow[step];
-        pa1 = prow[step + 1];
-        qa0 = qrow[step];
-        qa1 = qrow[step + 1];
-      }
+    // k-steps are fetched kBfPrefetch steps ahead into a ring of register
+    // sets (a fetch takes several steps' worth of MFMA time to arrive); the
+    // ring index is static because the step loop is unrolled by the ring
+    // size.  Fetches past the last step repeat it (their data is not used),
+    // so every load is unconditional.
+    u32x4 rb[kBfPrefetch][4];
+    auto fetch = [&](int s, u32x4 (&r)[4]) {
+      const int st = min(s, nsteps - 1) * (kBK / 8);  // in 16-byte units
+      r[0] = prow[st];
+      r[1] = prow[st + 1];
+      r[2] = qrow[st];
+      r[3] = qrow[st + 1];
+    };
+    // issued in ring order, as inside the loop: with the order differing
+    // between the first entry and the back edge the compiler could only
+    // wait for every outstanding load at the loop head
 #pragma unroll
-      for (int ks = 0; ks < kBK; ks += 16) {
-        const int kk = ks + 8 * (lane >> 5), rr = lane & 31;
-        const bf16x8 a0 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + rr][kk];
-        const bf16x8 a1 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + 32 + rr][kk];
-        const bf16x8 b0 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + rr][kk];
-        const bf16x8 b1 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + 32 + rr][kk];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    for (int p = 0; p < kBfPrefetch; ++p) {
+      fetch(p, rb[p]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int s0 = 0; s0 < nsteps; s0 += kBfPrefetch) {
+#pragma unroll
+      for (int p = 0; p < kBfPrefetch; ++p) {
+        // the fetch is outside the step's condition: with a conditional
+        // fetch the count of loads issued after a buffer's own would depend
+        // on the path, and the compiler then waited for all of them
+        const bool live = s0 + p < nsteps;
+        if (live) {
+          __syncthreads();
+          *(u32x4*)&sh.t.h.lp[sr][sk] = rb[p][0];
+          *(u32x4*)&sh.t.h.lp[sr][sk + 8] = rb[p][1];
+          *(u32x4*)&sh.t.h.lq[sr][sk] = rb[p][2];
+          *(u32x4*)&sh.t.h.lq[sr][sk + 8] = rb[p][3];
+          __syncthreads();
+        }
+        fetch(s0 + p + kBfPrefetch, rb[p]);
+        if (live) {
+#pragma unroll
+          for (int ks = 0; ks < kBK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5), rr = lane & 31;
+            const bf16x8 a0 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + rr][kk];
+            const bf16x8 a1 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + 32 + rr][kk];
+            const bf16x8 b0 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + rr][kk];
+            const bf16x8 b1 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + 32 + rr][kk];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+          }
+        }
       }
     }
     __syncthreads();
@@ -845,6 +911,7 @@ fastpfp_persistent(LaunchDesc L) {
   tm.seq = 0;
   tm.abort_flag = L.queue;
   tm.timeout = L.timeout_ticks;
+  tm.one_xcd = false;
   float* const Tt = L.wsT + (long long)tm.team * L.wsT_stride;
   float* const Yws = L.wsY + (long long)tm.team * L.wsY_stride;
   uint16_t* const Hws = L.wsH + (long long)tm.team * L.wsH_stride;
@@ -856,8 +923,12 @@ fastpfp_persistent(LaunchDesc L) {
                                    atomicAdd(L.queue + 1 + gi, 1u));
     __syncthreads();
     {
-      const float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
+      // the pair index, and this workgroup's XCD
+      const float post[kScal] = {sh.wred[0], (float)xcc_id(), 0.f, 0.f};
       if (!xchg_scalars(tm, sh, post)) return;
+      bool same = true;
+      for (int w = 1; w < tm.W; ++w) same &= sh.scal[w][1] == sh.scal[0][1];
+      tm.one_xcd = __builtin_amdgcn_readfirstlane((int)same) != 0;
     }
     const unsigned pidx =
         __builtin_amdgcn_readfirstlane(__float_as_uint(sh.scal[0][0]));
@@ -1116,9 +1187,9 @@ fastpfp_persistent(LaunchDesc L) {
         }
         {
           const float post[kScal] = {wg_max(sh, eloc), 0.f, 0.f, 0.f};
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          bulk_release(tm);
           if (!xchg_scalars(tm, sh, post)) return;
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          bulk_acquire(tm);
         }
         float e1 = 0.f;
         for (int w = 0; w < tm.W; ++w) e1 = fmaxf(e1, sh.scal[w][0]);
