@@ -27,8 +27,8 @@
 // tile row sums, column sums, tile totals and max|dY|: every 64-bit word
 // carries the exchange's sequence number in its high half, so the data itself
 // is the signal and no separate barrier or fence is needed.  Bulk data (T, Y,
-// X) crosses workgroups through global memory with release/acquire fences
-// around an exchange (L2-level when the team sits on one XCD).
+// X) crosses workgroups through global memory with agent-scope
+// release/acquire fences around an exchange.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -82,7 +82,6 @@ struct Team {
   unsigned seq;        // sequence number of the last exchange
   unsigned* abort_flag;
   long long timeout;   // wall clock ticks one wait may last
-  bool one_xcd;        // every workgroup of the team runs on the same XCD
 };
 
 constexpr int kGT = 128;  // GEMM output tile (kGT x kGT per workgroup)
@@ -221,41 +220,13 @@ __device__ bool xchg_scalars(Team& tm, Shared& sh, const float (&mine)[kScal]) {
   return __syncthreads_or(!ok) == 0;
 }
 
-// Fences around handing bulk data (T, Y, X, written with ordinary stores)
-// between the workgroups of a team.  A team whose workgroups all run on one
-// XCD shares that die's L2: a store is visible to the team once it has
-// reached L2 (its memory counter is zero), and a reader only has to drop its
-// own CU's L1 lines -- the same steps the compiler uses for a workgroup split
-// over CUs.  A team spread over several XCDs needs the agent-scope fences,
-// which write back and invalidate the whole L2 (also evicting the operands of
-// every other team on the die).
-__device__ __forceinline__ void bulk_release(const Team& tm) {
-  if (tm.one_xcd) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  }
-}
-__device__ __forceinline__ void bulk_acquire(const Team& tm) {
-  if (tm.one_xcd)
-    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
-  else
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-// Index of the XCD (accelerator complex die) this wave runs on.
-__device__ __forceinline__ int xcc_id() {
-  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // XCC_ID[3:0]
-}
-
 // Team barrier for bulk data written with ordinary stores: release fence,
 // scalar exchange, acquire fence.
 __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
-  bulk_release(tm);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   const float z[kScal] = {0.f, 0.f, 0.f, 0.f};
   const bool ok = xchg_scalars(tm, sh, z);
-  bulk_acquire(tm);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok;
 }
 
@@ -911,7 +882,6 @@ fastpfp_persistent(LaunchDesc L) {
   tm.seq = 0;
   tm.abort_flag = L.queue;
   tm.timeout = L.timeout_ticks;
-  tm.one_xcd = false;
   float* const Tt = L.wsT + (long long)tm.team * L.wsT_stride;
   float* const Yws = L.wsY + (long long)tm.team * L.wsY_stride;
   uint16_t* const Hws = L.wsH + (long long)tm.team * L.wsH_stride;
@@ -923,12 +893,8 @@ fastpfp_persistent(LaunchDesc L) {
                                    atomicAdd(L.queue + 1 + gi, 1u));
     __syncthreads();
     {
-      // the pair index, and this workgroup's XCD
-      const float post[kScal] = {sh.wred[0], (float)xcc_id(), 0.f, 0.f};
+      const float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
       if (!xchg_scalars(tm, sh, post)) return;
-      bool same = true;
-      for (int w = 1; w < tm.W; ++w) same &= sh.scal[w][1] == sh.scal[0][1];
-      tm.one_xcd = __builtin_amdgcn_readfirstlane((int)same) != 0;
     }
     const unsigned pidx =
         __builtin_amdgcn_readfirstlane(__float_as_uint(sh.scal[0][0]));
@@ -1187,9 +1153,9 @@ fastpfp_persistent(LaunchDesc L) {
         }
         {
           const float post[kScal] = {wg_max(sh, eloc), 0.f, 0.f, 0.f};
-          bulk_release(tm);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           if (!xchg_scalars(tm, sh, post)) return;
-          bulk_acquire(tm);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         float e1 = 0.f;
         for (int w = 0; w < tm.W; ++w) e1 = fmaxf(e1, sh.scal[w][0]);
