@@ -75,6 +75,10 @@ def parse():
                          "HBM byte counters) and exit")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the BF16, warm-start and ragged-batch legs")
+    ap.add_argument("--products-only", action="store_true",
+                    help="run only the products leg (8 outer steps x 1 inner "
+                         "pass on the metric set, FP32 and BF16) and print "
+                         "it as one JSON line")
     return ap.parse_args()
 
 
@@ -203,9 +207,9 @@ def ragged_batch(torch, F, steps):
 # summaries), each scaled by the factor the same counter reads for a plain
 # 1 GiB copy.  Valid only for the kernel source they were taken on.
 TRAFFIC = {"kernel_sha256":
-           "131a7448f6c5616ab3337d69df8dfa03fa6fe1d825c7c34ec45e22e364e697f6",
-           "fetch_kib": 16091352.5625 * 2.0,   # copy calibration: x 2.0
-           "write_kib": 22202137.75 * 1.0,     # copy calibration: x 1.0
+           "d167b30e76814ad603fd2176ffb15bda0a092045663c830bca719eb1e970edbd",
+           "fetch_kib": 15705541.3125 * 2.0,   # copy calibration: x 2.0
+           "write_kib": 21881715.21875 * 1.0,  # copy calibration: x 1.0
            "team_size": 16}
 
 
@@ -581,6 +585,12 @@ def main():
         tuned = {"chosen": team, "pair_passes_per_s": dict(cands)}
     prm = F.default_params(lambda_=1.0, team_size=team)
     ns, nps = [n] * args.pairs, [n] * args.pairs
+    if args.products_only:
+        res = products_leg(torch, F, S, ns, nps, A, B, K, X, offs, team,
+                           args.steps)
+        S.close()
+        print(json.dumps({"products": res, "team_size": team}), flush=True)
+        return
 
     def step():
         return S.solve_batched(ns, nps, A, offs, B, offs, K, offs, X, offs,
