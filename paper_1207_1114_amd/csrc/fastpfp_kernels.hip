@@ -116,6 +116,13 @@ struct Shared {
   double dtile[4];
 };
 
+// The workgroup's one Shared block.  Every function takes it from here, so
+// that the out-of-line projection below addresses it as LDS too.
+__device__ __forceinline__ Shared& shm() {
+  __shared__ Shared sh;
+  return sh;
+}
+
 // Value the compiler cannot see through: recomputed wherever it is used, so
 // per-element addresses and bounds masks derived from it are not hoisted out
 // of the solver's long-lived loops (which would pin hundreds of registers).
@@ -845,6 +852,114 @@ __device__ __forceinline__ float wg_max(Shared& sh, float v) {
   return fmaxf(fmaxf(sh.wred[0], sh.wred[1]), fmaxf(sh.wred[2], sh.wred[3]));
 }
 
+// ------------------------------------------------- out-of-line projection
+// Steps 4-7 on the team's N x N matrix Y in global memory: this workgroup's
+// tile is loaded, projected on chip and stored back.  A function of its own
+// so that the register allocation of the inner loop is not shared with the
+// solver's long-lived state (pair descriptor, step-3 and update addresses):
+// that state is saved once around the call instead of competing with the
+// tile's 128 registers in every pass.  Arguments arrive in vector registers;
+// they are uniform and moved to scalar registers first.
+struct ProjIn {
+  float* Y;
+  uint64_t* xb;
+  unsigned* abort_flag;
+  long long par_words, timeout;
+  int N, max_inner, W, TR, TC, tr, tc, rank, store_always;
+  unsigned seq;
+  float tol;
+};
+struct ProjOut {
+  unsigned seq;
+  int ok, numeric, passes, capped;
+  float eps2;
+};
+
+__device__ __forceinline__ int rfl(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ long long rfl64(long long v) {
+  const int lo = rfl((int)(v & 0xffffffffll)), hi = rfl((int)(v >> 32));
+  return ((long long)hi << 32) | (unsigned)lo;
+}
+template <class T>
+__device__ __forceinline__ T* rflp(T* p) {
+  return (T*)rfl64((long long)p);
+}
+
+template <bool kDyk>
+__device__ __attribute__((noinline)) ProjOut project_on_chip(ProjIn in) {
+  Shared& sh = shm();
+  const int tid = threadIdx.x, pr = tid >> 4, pc = tid & 15;
+  Team tm;
+  tm.team = 0;
+  tm.W = rfl(in.W);
+  tm.TR = rfl(in.TR);
+  tm.TC = rfl(in.TC);
+  tm.tr = rfl(in.tr);
+  tm.tc = rfl(in.tc);
+  tm.rank = rfl(in.rank);
+  tm.xb = rflp(in.xb);
+  tm.par_words = rfl64(in.par_words);
+  tm.seq = (unsigned)rfl((int)in.seq);
+  tm.abort_flag = rflp(in.abort_flag);
+  tm.timeout = rfl64(in.timeout);
+  const int N = rfl(in.N);
+  float* const Y = rflp(in.Y);
+  const TileGeom g = tile_geom(tm, N);
+  float Yr[kRegRows][kCB];
+  load_tile(Yr, sh, Y, N, g, pr, pc);
+  DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0ull, 0ull, 0ull};
+  bool numeric = false;
+  ProjOut o;
+  o.ok = inner_loop<kDyk>(Yr, tm, sh, g, rfl(in.max_inner),
+                          __int_as_float(rfl(__float_as_int(in.tol))), info,
+                          &numeric, pr, pc);
+  if (o.ok && (!numeric || rfl(in.store_always)))
+    store_tile(Yr, sh, Y, N, g, pr, pc);
+  o.seq = tm.seq;
+  o.numeric = numeric;
+  o.passes = info.inner_total;
+  o.capped = info.inner_capped;
+  o.eps2 = info.eps2;
+  return o;
+}
+
+// Runs project_on_chip for this workgroup of team tm and folds its counts
+// into info.  Returns false on abort; sets *numeric as inner_loop does.
+template <bool kDyk>
+__device__ __forceinline__ bool project_team(Team& tm, float* Y, int N,
+                                             int max_inner, float tol,
+                                             bool store_always, DevInfo& info,
+                                             bool* numeric) {
+  ProjIn in;
+  in.Y = Y;
+  in.xb = tm.xb;
+  in.abort_flag = tm.abort_flag;
+  in.par_words = tm.par_words;
+  in.timeout = tm.timeout;
+  in.N = N;
+  in.max_inner = max_inner;
+  in.W = tm.W;
+  in.TR = tm.TR;
+  in.TC = tm.TC;
+  in.tr = tm.tr;
+  in.tc = tm.tc;
+  in.rank = tm.rank;
+  in.store_always = store_always;
+  in.seq = tm.seq;
+  in.tol = tol;
+  const ProjOut o = project_on_chip<kDyk>(in);
+  tm.seq = (unsigned)rfl((int)o.seq);
+  *numeric = rfl(o.numeric) != 0;
+  const int u = rfl(o.passes);
+  info.inner_total += u;
+  info.inner_max = max(info.inner_max, u);
+  info.inner_capped += rfl(o.capped);
+  info.eps2 = __int_as_float(rfl(__float_as_int(o.eps2)));
+  return rfl(o.ok) != 0;
+}
+
 // --------------------------------------------------------------- the kernel
 // kDyk picks the inner projection: false runs Algorithm 1 as printed (plain
 // alternation of P1 and P2 in steps 4-7), true the exact projection
@@ -852,7 +967,7 @@ __device__ __forceinline__ float wg_max(Shared& sh, float v) {
 template <bool kDyk>
 __global__ void __launch_bounds__(kThreads, 1)
 fastpfp_persistent(LaunchDesc L) {
-  __shared__ Shared sh;
+  Shared& sh = shm();
   const int tid = threadIdx.x;
   const int pr = tid >> 4, pc = tid & 15;
 
@@ -908,13 +1023,11 @@ fastpfp_persistent(LaunchDesc L) {
     float Yr[kRegRows][kCB];
 
     if (pd.mode == kModeProject) {
-      load_tile(Yr, sh, Y, N, g, pr, pc);
       bool numeric = false;
-      if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
-                            &numeric, pr, pc))
+      if (!project_team<kDyk>(tm, Y, N, pd.max_inner, pd.tol_in, true, info,
+                              &numeric))
         return;
       info.t_proj = wall_clock64() - t_pair;
-      store_tile(Yr, sh, Y, N, g, pr, pc);
       info.status = numeric ? 5 : 0;
     } else {
       float* const X = pd.X;
@@ -1033,18 +1146,17 @@ fastpfp_persistent(LaunchDesc L) {
         if (!team_sync_bulk(tm, sh)) return;
         const unsigned long long t_gemm_end = wall_clock64();
         info.t_gemm += t_gemm_end - t_step;
-        // ---- steps 4-7
-        load_tile(Yr, sh, Y, N, g, pr, pc);
+        // ---- steps 4-7, then the projected tile back for steps 8-9
         bool numeric = false;
-        if (!inner_loop<kDyk>(Yr, tm, sh, g, pd.max_inner, pd.tol_in, info,
-                              &numeric, pr, pc))
+        if (!project_team<kDyk>(tm, Y, N, pd.max_inner, pd.tol_in, false, info,
+                                &numeric))
           return;
         info.t_proj += wall_clock64() - t_gemm_end;
         if (numeric) {
           info.status = 5;
           break;
         }
-        store_tile(Yr, sh, Y, N, g, pr, pc);
+        load_tile(Yr, sh, Y, N, g, pr, pc);
         // ---- step 8: X_new = (1 - alpha) X + alpha Y[:n,:np], kept in the
         // tile's storage
         const float alpha = pd.alpha, beta = 1.f - pd.alpha;
