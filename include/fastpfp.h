@@ -137,7 +137,10 @@ fastpfp_status fastpfp_params_default(fastpfp_params* p);
  * hipStream_t; NULL = the null stream).  max_n / max_np bound the sizes
  * later calls may pass (>= 1).  No device memory is allocated here; the
  * first handle on a device looks up that device's fixed scratch array of
- * fastpfp_solve_noalloc. */
+ * fastpfp_solve_noalloc.  The environment variable FASTPFP_EXCHANGE=agent,
+ * read here, makes the handle's solves exchange every inner pass's sums at
+ * device scope even for teams whose workgroups share one XCD (by default
+ * those teams post through that XCD's L2); results are the same either way. */
 fastpfp_status fastpfp_create(fastpfp_t* h, int device, int max_n, int max_np,
                               void* hip_stream);
 fastpfp_status fastpfp_destroy(fastpfp_t h);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -231,6 +232,7 @@ void fill_launch(fpfp::LaunchDesc* Lp, fastpfp_t h, char* base,
   L.wsH_stride = lay.wsH_stride;
   L.queue = (unsigned*)(base + lay.queue);
   L.timeout_ticks = 100000000LL * 20;  // 20 s of the 100 MHz wall clock
+  L.die_exchange = h->die_exchange;
 }
 
 // Copies one pair's device result into the public info struct.
@@ -582,6 +584,9 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
   if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate,
                             device) == hipSuccess && wall_khz > 0)
     h->wall_khz = wall_khz;
+  // FASTPFP_EXCHANGE=agent keeps every team's pass exchange at device scope
+  const char* xe = std::getenv("FASTPFP_EXCHANGE");
+  h->die_exchange = !(xe && std::strcmp(xe, "agent") == 0);
   // the device address of this device's fixed scratch array (looked up once
   // per device, with the device current)
   void* scratch = nullptr;

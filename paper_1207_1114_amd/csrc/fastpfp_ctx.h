@@ -25,6 +25,7 @@ struct fastpfp_ctx {
   int cu_count = 0;
   double wall_khz = 100000.0;  // device wall clock (s_memrealtime) rate
   int occupancy = 0;
+  int die_exchange = 1;        // 0: every team exchanges at device scope
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<double> trace;
   fpfp::WarmState* warm = nullptr;

@@ -77,6 +77,7 @@ struct LaunchDesc {
   long long wsH_stride;       // shadows, each Np x Np (Np = N rounded to 128)
   unsigned* queue;            // [0]: abort flag; [1 + g]: group g's next pair
   long long timeout_ticks;    // wall-clock ticks a wait may last
+  int die_exchange;           // teams found on one XCD post through its L2
 };
 
 // Exchange layout for one team and one parity buffer (u64 words):

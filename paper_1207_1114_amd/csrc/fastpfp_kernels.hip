@@ -52,19 +52,6 @@ __device__ __forceinline__ float unpack(uint64_t w) {
 __device__ __forceinline__ unsigned tag_of(uint64_t w) {
   return (unsigned)(w >> 32);
 }
-// The exchange words live in global memory.  Saying so lets the compiler use
-// global (not flat) stores and loads: a flat access may also reach LDS, and
-// the compiler then made every flat store of a post wait for all earlier
-// memory operations, so a workgroup's posts left one at a time.
-typedef __attribute__((address_space(1))) uint64_t gword;
-__device__ __forceinline__ void put_word(uint64_t* p, uint64_t v) {
-  __hip_atomic_store((gword*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t get_word(const uint64_t* p) {
-  return __hip_atomic_load((const gword*)p, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Global-memory view of a device pointer.  Every matrix the kernel reads or
 // writes is in device memory; through generic pointers those accesses become
 // flat instructions, which also count against the LDS counter, so a wait for
@@ -77,6 +64,7 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
 // Per-workgroup view of its team.
 struct Team {
   int team, rank, W, TR, TC, tr, tc;
+  int die;             // 1: every workgroup of the team runs on one XCD
   uint64_t* xb;        // this team's exchange words (both parities)
   long long par_words; // words per parity
   unsigned seq;        // sequence number of the last exchange
@@ -145,52 +133,96 @@ __device__ __forceinline__ bool timed_out(const Team& tm, long long& t0) {
   return false;
 }
 
+// Cache policy of the exchange words (cache bits of the buffer
+// instructions that move them).  Loads are always device-scope (sc1): they
+// skip the compute unit's L1, which would otherwise keep answering a poll
+// with the line it first fetched.  Agent: stores at device scope too, which
+// write through to the memory-side cache that every XCD reads.  Die: for a
+// team whose workgroups all run on one XCD, a plain store, which ends in that
+// XCD's L2, where the team's device-scope loads find it: a post-and-poll
+// round trip between two workgroups of one XCD measured 1217 cycles this way
+// against 2176 with device-scope stores (a plain store is not seen from
+// another XCD, whose L2 is separate).
+struct PolAgent {
+  static constexpr int ld = 16, st = 16;
+};
+struct PolDie {
+  static constexpr int ld = 16, st = 0;
+};
+
+// Exchange words are addressed as word offsets into the team's buffer.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t xrsrc(const Team& tm) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      tm.xb, 0, (int)(2 * tm.par_words * (long long)sizeof(uint64_t)),
+      0x00020000);
+}
+template <class P>
+__device__ __forceinline__ uint64_t ld_word(__amdgpu_buffer_rsrc_t r, int w) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, w * 8, 0, P::ld);
+  return ((uint64_t)v.y << 32) | v.x;
+}
+template <class P>
+__device__ __forceinline__ void st_word(__amdgpu_buffer_rsrc_t r, int w,
+                                        uint64_t v) {
+  u32x2 x;
+  x.x = (unsigned)v;
+  x.y = (unsigned)(v >> 32);
+  __builtin_amdgcn_raw_buffer_store_b64(x, r, w * 8, 0, P::st);
+}
+// Compiler-only barrier for memory operations: the buffer loads are not
+// atomics, so this keeps a post before the loads that wait for the other
+// workgroups' posts, and a polling load inside its loop.
+__device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
+
 // Gathers three strided runs of exchange words -- nr (<= 8) words at
-// base_r + k*str_r, nc (<= 8) at base_c + k*str_c and ns (<= kScal) at
-// base_s + k -- until all carry tag `seq`.  All loads are issued together;
+// off_r + k*str_r, nc (<= 8) at off_c + k*str_c and ns (<= kScal) at
+// off_s + k -- until all carry tag `seq`.  All loads are issued together;
 // while data is missing only one outstanding word is polled, then the
 // missing ones are reissued.  Returns false on abort or timeout.
 constexpr int kMaxRun = 8;
-__device__ __forceinline__ bool gather3(const uint64_t* base_r, long long str_r,
-                                        int nr, const uint64_t* base_c,
-                                        long long str_c, int nc,
-                                        const uint64_t* base_s, int ns,
+template <class P>
+__device__ __forceinline__ bool gather3(__amdgpu_buffer_rsrc_t rs, int off_r,
+                                        int str_r, int nr, int off_c,
+                                        int str_c, int nc, int off_s, int ns,
                                         unsigned seq, float* rsum, float* csum,
                                         float (&sv)[kScal], const Team& tm) {
   const uint64_t done = (uint64_t)seq << 32;
   uint64_t vr[kMaxRun], vc[kMaxRun], vs[kScal];
 #pragma unroll
   for (int k = 0; k < kMaxRun; ++k) {
-    vr[k] = (k < nr) ? get_word(base_r + k * str_r) : done;
-    vc[k] = (k < nc) ? get_word(base_c + k * str_c) : done;
+    vr[k] = (k < nr) ? ld_word<P>(rs, off_r + k * str_r) : done;
+    vc[k] = (k < nc) ? ld_word<P>(rs, off_c + k * str_c) : done;
   }
 #pragma unroll
-  for (int k = 0; k < kScal; ++k) vs[k] = (k < ns) ? get_word(base_s + k) : done;
+  for (int k = 0; k < kScal; ++k)
+    vs[k] = (k < ns) ? ld_word<P>(rs, off_s + k) : done;
   long long t0 = 0;
   for (;;) {
-    const uint64_t* wait_on = nullptr;
+    int wait_on = -1;
 #pragma unroll
     for (int k = kScal - 1; k >= 0; --k)
-      if (tag_of(vs[k]) != seq) wait_on = base_s + k;
+      if (tag_of(vs[k]) != seq) wait_on = off_s + k;
 #pragma unroll
     for (int k = kMaxRun - 1; k >= 0; --k) {
-      if (tag_of(vc[k]) != seq) wait_on = base_c + k * str_c;
-      if (tag_of(vr[k]) != seq) wait_on = base_r + k * str_r;
+      if (tag_of(vc[k]) != seq) wait_on = off_c + k * str_c;
+      if (tag_of(vr[k]) != seq) wait_on = off_r + k * str_r;
     }
-    if (!wait_on) break;
+    if (wait_on < 0) break;
     int spins = 0;
-    while (tag_of(get_word(wait_on)) != seq) {
+    while (tag_of(ld_word<P>(rs, wait_on)) != seq) {
       __builtin_amdgcn_s_sleep(1);
+      mem_order();
       if ((++spins & 31) == 0 && timed_out(tm, t0)) return false;
     }
 #pragma unroll
     for (int k = 0; k < kMaxRun; ++k) {
-      if (tag_of(vr[k]) != seq) vr[k] = get_word(base_r + k * str_r);
-      if (tag_of(vc[k]) != seq) vc[k] = get_word(base_c + k * str_c);
+      if (tag_of(vr[k]) != seq) vr[k] = ld_word<P>(rs, off_r + k * str_r);
+      if (tag_of(vc[k]) != seq) vc[k] = ld_word<P>(rs, off_c + k * str_c);
     }
 #pragma unroll
     for (int k = 0; k < kScal; ++k)
-      if (tag_of(vs[k]) != seq) vs[k] = get_word(base_s + k);
+      if (tag_of(vs[k]) != seq) vs[k] = ld_word<P>(rs, off_s + k);
   }
   float r = 0.f, c = 0.f;
 #pragma unroll
@@ -209,18 +241,20 @@ __device__ __forceinline__ bool gather3(const uint64_t* base_r, long long str_r,
 // holds workgroup w's values for this sequence number.
 __device__ bool xchg_scalars(Team& tm, Shared& sh, const float (&mine)[kScal]) {
   const unsigned seq = ++tm.seq;
-  uint64_t* base = tm.xb + (seq & 1u) * tm.par_words +
-                   (tm.par_words - (long long)tm.W * kScal);
+  const __amdgpu_buffer_rsrc_t rs = xrsrc(tm);
+  const int base = (int)((seq & 1u) * tm.par_words + tm.par_words) -
+                   tm.W * kScal;
   __syncthreads();
   if (threadIdx.x < kScal)
-    put_word(base + tm.rank * kScal + threadIdx.x,
-             pack(seq, mine[threadIdx.x]));
+    st_word<PolAgent>(rs, base + tm.rank * kScal + threadIdx.x,
+                      pack(seq, mine[threadIdx.x]));
+  mem_order();
   const int w = threadIdx.x;
   bool ok = true;
   if (w < tm.W) {
     float sv[kScal], r, c;
-    ok = gather3(base, 0, 0, base, 0, 0, base + w * kScal, kScal, seq, &r, &c,
-                 sv, tm);
+    ok = gather3<PolAgent>(rs, 0, 0, 0, 0, 0, 0, base + w * kScal, kScal, seq,
+                           &r, &c, sv, tm);
 #pragma unroll
     for (int k = 0; k < kScal; ++k) sh.scal[w][k] = sv[k];
   }
@@ -532,10 +566,11 @@ __device__ __forceinline__ float row16_sum(float v) {
 // Cycles to sleep (in units of 64 clocks) between posting an exchange and
 // the first load of it: about one store-to-visibility latency, so the first
 // loads usually find the data instead of polling.  Measured with 16 teams of
-// 16 at n = 1000 (in-solve pass time): 3 -> 8.08 us, 8 -> 8.06, 16 -> 7.53,
-// 24 -> 7.71, 32 -> 7.92, 48 -> 8.34; shorter sleeps add polling traffic that
-// slows every team.
-constexpr int kPostSleep = 16;
+// 16 at n = 1000 (in-solve pass time), device-scope posts: 3 -> 8.08 us,
+// 8 -> 8.06, 16 -> 7.53, 24 -> 7.71, 32 -> 7.92, 48 -> 8.34 (shorter sleeps
+// add polling traffic that slows every team); posts through one XCD's L2:
+// 4 -> 6.90, 8 -> 6.89, 16 -> 6.91.
+constexpr int kPostSleep = 8;
 
 // One team exchange of a pass.  In: each thread's row partials rs[a] (over
 // its kCB columns), column partials cs[b] (over its kRA rows) and its
@@ -545,6 +580,7 @@ constexpr int kPostSleep = 16;
 // gathers the full row sums of the tile's rows, column sums of its columns,
 // s = 1^T Y 1 and the team's max|dY|.  Leaves a (rows) and b (columns) of P1
 // in sh.a_l / sh.b_l.  Returns false on abort.
+template <class P>
 __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
                               const float (&rs)[kRA], const float (&cs)[kCB],
                               float dm, double* s_out, float* dmax_out) {
@@ -593,43 +629,37 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
     dmax = dmw;
   } else {
     const unsigned seq = ++tm.seq;
-    uint64_t* buf = tm.xb + (seq & 1u) * tm.par_words;
-    const long long NPR = (long long)tm.TR * g.h, NPC = (long long)tm.TC * g.w;
-    uint64_t* rowp = buf;                        // [TC][NPR]
-    uint64_t* colp = buf + tm.TC * NPR;          // [TR][NPC]
-    uint64_t* scal = buf + (tm.par_words - (long long)tm.W * kScal);
+    const __amdgpu_buffer_rsrc_t rs = xrsrc(tm);
+    const int buf = (int)((seq & 1u) * tm.par_words);
+    const int NPR = tm.TR * g.h, NPC = tm.TC * g.w;
+    const int rowp = buf;                        // [TC][NPR]
+    const int colp = buf + tm.TC * NPR;          // [TR][NPC]
+    const int scal = buf + (int)tm.par_words - tm.W * kScal;
     __syncthreads();  // the four waves' tile partials in sh.dtile
     // Every address and word of this thread's posts is formed first and the
     // stores then issue back to back: the memory counter also counts stores,
     // so a spill reload between two posts of a thread would hold the second
     // until the first is acknowledged.
-    uint64_t* ra = rowp + tm.tc * NPR + g.r0 + t;
-    uint64_t* ca = colp + tm.tr * NPC + g.c0 + t;
-    uint64_t* sa = scal + tm.rank * kScal;
-    int post_r = t < g.h, post_c = t < g.w, post_s = tid == 0;
-    uint64_t wr = pack(seq, rpart), wc = pack(seq, cpart);
-    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    int ra = rowp + tm.tc * NPR + g.r0 + t;
+    int ca = colp + tm.tr * NPC + g.c0 + t;
+    // the tile's scalars: lane k < kScal of wave 0 posts word k (one 64-bit
+    // word per lane, so no two words share a store)
+    int sa = scal + tm.rank * kScal + tid;
+    int post_r = t < g.h, post_c = t < g.w, post_s = tid < kScal;
+    uint64_t wr = pack(seq, rpart), wc = pack(seq, cpart), ws = 0;
     if (post_s) {
       const double ttot = ((sh.dtile[0] + sh.dtile[1]) + sh.dtile[2]) +
                           sh.dtile[3];
       const float hi = (float)ttot;
       const float lo = (float)(ttot - (double)hi);
-      w0 = pack(seq, hi);
-      w1 = pack(seq, lo);
-      w2 = pack(seq, dmw);
-      w3 = pack(seq, 0.f);
+      ws = pack(seq, tid == 0 ? hi : tid == 1 ? lo : tid == 2 ? dmw : 0.f);
     }
     asm volatile("" : "+v"(ra), "+v"(ca), "+v"(sa), "+v"(post_r),
-                 "+v"(post_c), "+v"(post_s), "+v"(wr), "+v"(wc), "+v"(w0),
-                 "+v"(w1), "+v"(w2), "+v"(w3));
-    if (post_r) put_word(ra, wr);
-    if (post_c) put_word(ca, wc);
-    if (post_s) {
-      put_word(sa + 0, w0);
-      put_word(sa + 1, w1);
-      put_word(sa + 2, w2);
-      put_word(sa + 3, w3);
-    }
+                 "+v"(post_c), "+v"(post_s), "+v"(wr), "+v"(wc), "+v"(ws));
+    if (post_r) st_word<P>(rs, ra, wr);
+    if (post_c) st_word<P>(rs, ca, wc);
+    if (post_s) st_word<P>(rs, sa, ws);
+    mem_order();
     __builtin_amdgcn_s_sleep(kPostSleep);
     // this thread's runs: TC row partials of row t and TR column partials of
     // column t (in chunks of 8), plus workgroup t's scalars
@@ -640,10 +670,10 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
     for (int k0 = 0; k0 < max(max(nr, nc), 1) && ok; k0 += kMaxRun) {
       float r, c, sv[kScal];
       const bool first = k0 == 0;
-      ok = gather3(rowp + k0 * NPR + g.r0 + t, NPR, min(kMaxRun, nr - k0),
-                   colp + k0 * NPC + g.c0 + t, NPC, min(kMaxRun, nc - k0),
-                   scal + tid * kScal, (first && tid < tm.W) ? kScal : 0, seq,
-                   &r, &c, sv, tm);
+      ok = gather3<P>(rs, rowp + k0 * NPR + g.r0 + t, NPR,
+                      min(kMaxRun, nr - k0), colp + k0 * NPC + g.c0 + t, NPC,
+                      min(kMaxRun, nc - k0), scal + tid * kScal,
+                      (first && tid < tm.W) ? kScal : 0, seq, &r, &c, sv, tm);
       rfull += r;
       cfull += c;
       if (first && tid < tm.W) {
@@ -732,7 +762,7 @@ __device__ __forceinline__ void store_tile(const float (&Yr)[kRegRows][kCB],
 // w <- w + a 1^T + 1 b^T with a, b from the sums of x, and x = max(w, 0)
 // when the loop ends.  The first pass starts from x = Y itself, as the plain
 // loop does; max|dx| is the stopping measure.
-template <bool kDyk>
+template <bool kDyk, class P>
 __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
                                            Team& tm, Shared& sh,
                                            const TileGeom& g, int max_inner,
@@ -753,7 +783,7 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
     }
   double s;
   float d = 0.f;
-  if (!exchange_sums(tm, sh, g, rs, cs, 0.f, &s, &d)) return false;
+  if (!exchange_sums<P>(tm, sh, g, rs, cs, 0.f, &s, &d)) return false;
   *numeric = !isfinite(s);
   int u = 0;
   d = 0.f;
@@ -815,7 +845,7 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
         }
         rs[a] = r;
       }
-      if (!exchange_sums(tm, sh, g, rs, cs, dm, &s, &d)) return false;
+      if (!exchange_sums<P>(tm, sh, g, rs, cs, dm, &s, &d)) return false;
       if (!isfinite(s) || !isfinite(d)) {
         *numeric = true;
         break;
@@ -887,12 +917,13 @@ __device__ __forceinline__ T* rflp(T* p) {
   return (T*)rfl64((long long)p);
 }
 
-template <bool kDyk>
+template <bool kDyk, class P>
 __device__ __attribute__((noinline)) ProjOut project_on_chip(ProjIn in) {
   Shared& sh = shm();
   const int tid = threadIdx.x, pr = tid >> 4, pc = tid & 15;
   Team tm;
   tm.team = 0;
+  tm.die = 0;  // the policy is the template argument
   tm.W = rfl(in.W);
   tm.TR = rfl(in.TR);
   tm.TC = rfl(in.TC);
@@ -912,7 +943,7 @@ __device__ __attribute__((noinline)) ProjOut project_on_chip(ProjIn in) {
   DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0ull, 0ull, 0ull};
   bool numeric = false;
   ProjOut o;
-  o.ok = inner_loop<kDyk>(Yr, tm, sh, g, rfl(in.max_inner),
+  o.ok = inner_loop<kDyk, P>(Yr, tm, sh, g, rfl(in.max_inner),
                           __int_as_float(rfl(__float_as_int(in.tol))), info,
                           &numeric, pr, pc);
   if (o.ok && (!numeric || rfl(in.store_always)))
@@ -949,7 +980,8 @@ __device__ __forceinline__ bool project_team(Team& tm, float* Y, int N,
   in.store_always = store_always;
   in.seq = tm.seq;
   in.tol = tol;
-  const ProjOut o = project_on_chip<kDyk>(in);
+  const ProjOut o = tm.die ? project_on_chip<kDyk, PolDie>(in)
+                            : project_on_chip<kDyk, PolAgent>(in);
   tm.seq = (unsigned)rfl((int)o.seq);
   *numeric = rfl(o.numeric) != 0;
   const int u = rfl(o.passes);
@@ -995,6 +1027,7 @@ fastpfp_persistent(LaunchDesc L) {
   tm.xb = L.xbuf + (long long)tm.team * L.xbuf_stride;
   tm.par_words = L.xbuf_stride / 2;
   tm.seq = 0;
+  tm.die = 0;
   tm.abort_flag = L.queue;
   tm.timeout = L.timeout_ticks;
   float* const Tt = L.wsT + (long long)tm.team * L.wsT_stride;
@@ -1008,12 +1041,22 @@ fastpfp_persistent(LaunchDesc L) {
                                    atomicAdd(L.queue + 1 + gi, 1u));
     __syncthreads();
     {
-      const float post[kScal] = {sh.wred[0], 0.f, 0.f, 0.f};
+      // with it, each workgroup posts the XCD it runs on (hardware register
+      // XCC_ID, bits 3:0)
+      const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20);
+      const float post[kScal] = {sh.wred[0], __uint_as_float(xcc), 0.f, 0.f};
       if (!xchg_scalars(tm, sh, post)) return;
     }
     const unsigned pidx =
         __builtin_amdgcn_readfirstlane(__float_as_uint(sh.scal[0][0]));
     if (pidx >= (unsigned)grp.pair_end) return;
+    {
+      // a team on one XCD exchanges its pass sums through that XCD's L2
+      int same = 1;
+      for (int w = 1; w < tm.W; ++w)
+        same &= __float_as_uint(sh.scal[w][1]) == __float_as_uint(sh.scal[0][1]);
+      tm.die = __builtin_amdgcn_readfirstlane(same && L.die_exchange);
+    }
     const PairDesc& pd = L.pairs[pidx];
     const int n = pd.n, np = pd.np, N = pd.N;
     float* const Y = pd.Y ? pd.Y : Yws;
