@@ -762,7 +762,7 @@ __device__ __forceinline__ void store_tile(const float (&Yr)[kRegRows][kCB],
 // w <- w + a 1^T + 1 b^T with a, b from the sums of x, and x = max(w, 0)
 // when the loop ends.  The first pass starts from x = Y itself, as the plain
 // loop does; max|dx| is the stopping measure.
-template <bool kDyk, class P>
+template <bool kDyk, class P, bool kPart>
 __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
                                            Team& tm, Shared& sh,
                                            const TileGeom& g, int max_inner,
@@ -787,6 +787,8 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
   *numeric = !isfinite(s);
   int u = 0;
   d = 0.f;
+  // rows a < amax hold every row of the tile inside N
+  const int amax = __builtin_amdgcn_readfirstlane((g.hv + 15) >> 4);
   if (!*numeric) {
     for (u = 1; u <= max_inner; ++u) {
       // LDS reads are issued well ahead of their use (one wave per SIMD has
@@ -806,10 +808,17 @@ __device__ __forceinline__ bool inner_loop(float (&Yr)[kRegRows][kCB],
       const float lo = (kDyk && u == 1) ? -INFINITY : 0.f;
 #pragma unroll
       for (int b = 0; b < kCB; ++b) cs[b] = 0.f;
+      if constexpr (kPart) {
+#pragma unroll
+        for (int a = 0; a < kRA; ++a) rs[a] = 0.f;
+      }
 #pragma unroll
       for (int a = 0; a < kRA; ++a) {
         const float av_a = av_next;
         if (a + 1 < kRA) av_next = sh.a_l[pr + 16 * (a + 1)];
+        // a partial tile skips its padding rows, whose entries stay exactly
+        // 0 (a uniform branch; rs of a skipped row is 0)
+        if (kPart && a >= amax) break;
         float r = 0.f;
 #pragma unroll
         for (int b = 0; b < kCB; ++b) {
@@ -917,7 +926,7 @@ __device__ __forceinline__ T* rflp(T* p) {
   return (T*)rfl64((long long)p);
 }
 
-template <bool kDyk, class P>
+template <bool kDyk, class P, bool kPart>
 __device__ __attribute__((noinline)) ProjOut project_on_chip(ProjIn in) {
   Shared& sh = shm();
   const int tid = threadIdx.x, pr = tid >> 4, pc = tid & 15;
@@ -943,7 +952,7 @@ __device__ __attribute__((noinline)) ProjOut project_on_chip(ProjIn in) {
   DevInfo info = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0ull, 0ull, 0ull};
   bool numeric = false;
   ProjOut o;
-  o.ok = inner_loop<kDyk, P>(Yr, tm, sh, g, rfl(in.max_inner),
+  o.ok = inner_loop<kDyk, P, kPart>(Yr, tm, sh, g, rfl(in.max_inner),
                           __int_as_float(rfl(__float_as_int(in.tol))), info,
                           &numeric, pr, pc);
   if (o.ok && (!numeric || rfl(in.store_always)))
@@ -980,8 +989,16 @@ __device__ __forceinline__ bool project_team(Team& tm, float* Y, int N,
   in.store_always = store_always;
   in.seq = tm.seq;
   in.tol = tol;
-  const ProjOut o = tm.die ? project_on_chip<kDyk, PolDie>(in)
-                            : project_on_chip<kDyk, PolAgent>(in);
+  // tiles with padding rows take the sweep that skips them (skipping
+  // padding columns too, in groups, broke the sweep into blocks too short
+  // to schedule well and was slower at most sizes)
+  const TileGeom g = tile_geom(tm, N);
+  const bool part = g.hv <= kTileRows - 16;
+  const ProjOut o =
+      tm.die ? (!part ? project_on_chip<kDyk, PolDie, false>(in)
+                      : project_on_chip<kDyk, PolDie, true>(in))
+             : (!part ? project_on_chip<kDyk, PolAgent, false>(in)
+                      : project_on_chip<kDyk, PolAgent, true>(in));
   tm.seq = (unsigned)rfl((int)o.seq);
   *numeric = rfl(o.numeric) != 0;
   const int u = rfl(o.passes);
