@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <queue>
 #include <vector>
 
 #include "fastpfp.h"
@@ -210,6 +211,33 @@ void fill_pair(fpfp::PairDesc* dp, const PairIn& q, const fastpfp_params* p,
   }
 }
 
+// Modelled time (microseconds) of one inner pass of a team of W workgroups
+// (TR tile rows) on an N x N matrix: a fixed part -- the workgroup's
+// reductions, and for W > 1 the team exchange -- plus the sweep over the
+// tile rows that hold entries (the sweep skips padding rows).  Fitted to
+// passes measured on MI355X at W = 1, 4 and 16 and N = 16 ... 1000; used only
+// to divide a mixed batch's workgroups between its team sizes.
+double pass_cost(int W, int TR, int N) {
+  const int h = (N + TR - 1) / TR;
+  const int rows = (std::min(h, fpfp::kTileRows) + 15) / 16;
+  return (W == 1 ? 1.6 : 4.2) + 3.0 * rows / 16.0;
+}
+
+// Time until the last of `costs` (sorted largest first) is done when
+// `teams` teams take them from one queue in that order.
+double lpt_makespan(const std::vector<double>& costs, int teams) {
+  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+  for (int k = 0; k < teams; ++k) q.push(0.0);
+  double end = 0.0;
+  for (double c : costs) {
+    const double t = q.top() + c;
+    q.pop();
+    q.push(t);
+    end = std::max(end, t);
+  }
+  return end;
+}
+
 // The launch descriptor over a workspace at `base` laid out as `lay`.
 void fill_launch(fpfp::LaunchDesc* Lp, fastpfp_t h, char* base,
                  const Layout& lay, int P, int NG, const fpfp::TeamGroup* grp,
@@ -291,37 +319,38 @@ fastpfp_status run(fastpfp_t h, const std::vector<PairIn>& pairs,
     return fail(h, FASTPFP_ERR_UNSUPPORTED, "too many team sizes in a batch");
   const int NG = (int)sizes.size();
   std::vector<std::vector<int>> members(NG);
-  std::vector<double> work(NG, 0.0);
+  std::vector<std::vector<double>> cost(NG);
   for (int b = 0; b < P; ++b) {
     const int g = (int)(std::find(sizes.begin(), sizes.end(), pplan[b].W) -
                         sizes.begin());
     members[g].push_back(b);
-    const double Nb = std::max(pairs[b].n, pairs[b].np);
-    work[g] += Nb * Nb;
+    cost[g].push_back(pass_cost(pplan[b].W, pplan[b].TR,
+                                std::max(pairs[b].n, pairs[b].np)));
   }
+  for (auto& c : cost) std::sort(c.rbegin(), c.rend());
   int need = 0;
   for (int g = 0; g < NG; ++g) need += sizes[g];
   if (need > G)
     return fail(h, FASTPFP_ERR_UNSUPPORTED,
                 "a batch needs %d co-resident workgroups; %d fit", need, G);
-  // workgroups in proportion to work, at least one team per group, at most
-  // one team per pair
-  double wsum = 0.0;
-  for (double w : work) wsum += w;
-  std::vector<int> teams(NG);
-  int used = 0;
-  for (int g = 0; g < NG; ++g) {
-    const int share = (int)((double)G * work[g] / wsum);
-    teams[g] = std::max(1, std::min((int)members[g].size(), share / sizes[g]));
-    used += teams[g] * sizes[g];
-  }
-  while (used > G) {  // trim the group with the most spare teams
-    int best = -1;
-    for (int g = 0; g < NG; ++g)
-      if (teams[g] > 1 && (best < 0 || teams[g] * sizes[g] > teams[best] * sizes[best]))
-        best = g;
-    teams[best]--;
-    used -= sizes[best];
+  // One team per group to start with; then, while workgroups are free, one
+  // more team for the group whose pairs (modelled pass costs, taken from its
+  // queue largest first) would finish last, as long as it has a pair for the
+  // team.  A group that cannot grow any more ends the search, since the
+  // batch cannot finish before it.
+  std::vector<int> teams(NG, 1);
+  std::vector<double> span(NG);
+  int used = need;
+  for (int g = 0; g < NG; ++g) span[g] = lpt_makespan(cost[g], 1);
+  for (;;) {
+    int worst = 0;
+    for (int g = 1; g < NG; ++g)
+      if (span[g] > span[worst]) worst = g;
+    if (used + sizes[worst] > G || teams[worst] >= (int)members[worst].size())
+      break;
+    teams[worst]++;
+    used += sizes[worst];
+    span[worst] = lpt_makespan(cost[worst], teams[worst]);
   }
   for (bool grew = true; grew;) {  // hand out what is left
     grew = false;
