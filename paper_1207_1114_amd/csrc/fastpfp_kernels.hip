@@ -682,24 +682,19 @@ __device__ bool exchange_sums(Team& tm, Shared& sh, const TileGeom& g,
       }
     }
     if (__syncthreads_or(!ok)) return false;
-    // team scalars: s in float64 (fixed order), max|dY|
-    if (wave == 0) {
+    // team scalars: s in float64 (fixed order), max|dY|; every wave reduces
+    // the same words in the same order, so all get the same bits without
+    // another barrier
+    {
       double tsum = 0.0;
       float m = 0.f;
       for (int w = lane; w < tm.W; w += 64) {
         tsum += (double)sh.scal[w][0] + (double)sh.scal[w][1];
         m = fmaxf(m, sh.scal[w][2]);
       }
-      tsum = wave_sum_d(tsum);
-      m = wave_max(m);
-      if (lane == 0) {
-        sh.dred[0] = tsum;
-        sh.wred[0] = m;
-      }
+      s = wave_sum_d(tsum);
+      dmax = wave_max(m);
     }
-    __syncthreads();
-    s = sh.dred[0];
-    dmax = sh.wred[0];
   }
   sh.a_l[t] = (t < g.hv) ? (float)((1.0 - (double)rfull) * invN +
                                    (s - Nd) * invN * invN)
