@@ -33,9 +33,11 @@ def dev(torch, a):
 
 
 @pytest.mark.parametrize("N,T,team", [(1, 5, 0), (2, 40, 0), (17, 120, 0),
-                                      (129, 60, 0), (257, 40, 0),
-                                      (300, 40, 0), (300, 40, 16),
-                                      (513, 30, 0), (1000, 20, 0)])
+                                      (129, 60, 0), (200, 30, 0),
+                                      (257, 40, 0), (300, 40, 0),
+                                      (300, 40, 16), (470, 30, 0),
+                                      (513, 30, 0), (900, 20, 0),
+                                      (1000, 20, 0)])
 def test_dykstra_projection_parity(env, N, T, team):
     torch, F, S = env
     rng = np.random.default_rng([N, T, 7])

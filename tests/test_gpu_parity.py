@@ -49,11 +49,17 @@ def gpu_solve(env, p, prm=None, X0=None, Y0=None, **kw):
 
 
 # ------------------------------------------------------------ projection
+# N past 128, 256 and 512 in steps that give a workgroup's tile 9 ... 15
+# rows of 16 that hold entries (the sweep skips the rest) for teams of 1, 4
+# and 16 workgroups
 @pytest.mark.parametrize("N,T,team", [(1, 5, 0), (2, 40, 0), (17, 120, 0),
-                                      (129, 60, 0), (257, 40, 0),
-                                      (300, 40, 0), (300, 40, 16),
-                                      (513, 30, 0), (1000, 20, 0),
-                                      (1000, 20, 64)])
+                                      (129, 60, 0), (160, 30, 0),
+                                      (200, 30, 0), (240, 30, 0),
+                                      (257, 40, 0), (300, 40, 0),
+                                      (300, 40, 16), (350, 30, 0),
+                                      (470, 30, 0), (513, 30, 0),
+                                      (700, 20, 0), (900, 20, 0),
+                                      (1000, 20, 0), (1000, 20, 64)])
 def test_projection_parity(env, N, T, team):
     torch, F, S = env
     rng = np.random.default_rng([N, T])
