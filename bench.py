@@ -207,9 +207,9 @@ def ragged_batch(torch, F, steps):
 # summaries), each scaled by the factor the same counter reads for a plain
 # 1 GiB copy.  Valid only for the kernel source they were taken on.
 TRAFFIC = {"kernel_sha256":
-           "d167b30e76814ad603fd2176ffb15bda0a092045663c830bca719eb1e970edbd",
-           "fetch_kib": 15705541.3125 * 2.0,   # copy calibration: x 2.0
-           "write_kib": 21881715.21875 * 1.0,  # copy calibration: x 1.0
+           "6c8de3e2fc44246791e73d331d31d04f267d5f123dd5d6355493a0fcfdfbff15",
+           "fetch_kib": 7728305.6875 * 2.0,    # copy calibration: x 2.0
+           "write_kib": 4846458.3125 * 1.0,    # copy calibration: x 1.0
            "team_size": 16}
 
 
