@@ -262,6 +262,19 @@ def products_leg(torch, F, S, ns, nps, A, B, K, X, offs, team, steps):
     return out
 
 
+def products_large(torch, F, steps, n=4000):
+    """The products leg at n = n' = 4000 (configuration 4's largest size):
+    one synthetic pair on one team of every compute unit, the only team that
+    holds N = 4000 on chip."""
+    _, A, B, K, X, offs = make_inputs(torch, 1, n)
+    S = F.Solver(n, n)
+    team, _ = S.autotune(n, 1)
+    res = products_leg(torch, F, S, [n], [n], A, B, K, X, offs, team, steps)
+    S.close()
+    res["n"] = n
+    return res
+
+
 def warm_leg(torch, F, pairs, steps, team):
     """BF16 products from the learned warm start on the same pairs as the
     FP32 leg: the timed step is the batched warm start (X0 of every pair),
@@ -713,6 +726,7 @@ def main():
         out["config3"] = ragged_batch(torch, F, args.steps)
         out["products"] = products_leg(torch, F, S, ns, nps, A, B, K, X, offs,
                                        team, args.steps)
+        out["products_n4000"] = products_large(torch, F, args.steps)
     S.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pairs[0], infos, args.cpu_passes,

@@ -75,10 +75,10 @@ struct Team {
 constexpr int kGT = 128;  // GEMM output tile (kGT x kGT per workgroup)
 constexpr int kGK = 16;   // GEMM k-rows staged per step
 constexpr int kBK = 32;   // BF16 GEMM k per step
-#ifndef FPFP_BF16_PREFETCH
-#define FPFP_BF16_PREFETCH 2
+#ifndef FPFP_BF16_STAGES
+#define FPFP_BF16_STAGES 4
 #endif
-constexpr int kBfPrefetch = FPFP_BF16_PREFETCH;  // BF16 k-steps fetched ahead
+constexpr int kBfStages = FPFP_BF16_STAGES;  // BF16 k-steps held in LDS
 
 struct Shared {
   union {
@@ -89,9 +89,9 @@ struct Shared {
       float lp[kGK][kGT];
       float lq[kGK][kGT];
     } g;
-    struct {  // BF16 GEMM staging: [row][k], 32 k per step, padded pitch
-      uint16_t lp[kGT][kBK + 8];
-      uint16_t lq[kGT][kBK + 8];
+    struct {  // BF16 GEMM staging: a ring of k-steps, each the two
+              // operands' kGT x kBK slices as 16-byte chunks
+      uint16_t ring[kBfStages][2][kGT * kBK];
     } h;
   } t;
   float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
@@ -273,6 +273,50 @@ __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
 }
 
 // ------------------------------------------------------------------- GEMM
+// Output tile of a team product for work index q (rank + i * W in round i).
+// When a team spans whole XCDs, row-major order gives the 32 ranks on one
+// XCD a strip of one or two tile rows by every tile column (at n = 4000:
+// one by 32), so their L2 holds a slice of every column panel.  When the
+// grid divides into blocks of xg = gm x gn tiles, q instead walks the grid
+// block by block, and the xg ranks of an XCD take one near-square block in
+// each round (4 x 8 tiles for 32 ranks: 12 operand panels instead of 33).
+// Teams smaller than an XCD keep row-major order (16 ranks cover 10 panels
+// in it, 8 in blocks, and measured no faster).  Every tile is still
+// computed once, by the same instructions, so results do not depend on the
+// order.  The block size assumes 32 compute units per XCD, as on MI355X;
+// elsewhere it is only a worse order.
+constexpr int kXcdRanks = 32;
+__device__ __forceinline__ int xcd_ranks(int W) {
+  return W >= kXcdRanks ? kXcdRanks : 1;
+}
+struct TileMap {
+  int tiles_n, gm, gn, bn, blocked;
+};
+__device__ __forceinline__ TileMap tile_map(int tiles_m, int tiles_n,
+                                            int xg) {
+  TileMap t;
+  t.tiles_n = tiles_n;
+  int lg = 0;
+  while ((2 << lg) <= xg) ++lg;  // xg = 2^lg for the powers of two used
+  t.gm = 1 << (lg / 2);
+  t.gn = xg / t.gm;
+  t.blocked = xg >= 32 && (xg & (xg - 1)) == 0 && tiles_m % t.gm == 0 &&
+              tiles_n % t.gn == 0;
+  t.bn = t.blocked ? tiles_n / t.gn : 1;
+  return t;
+}
+__device__ __forceinline__ void tile_of(const TileMap& t, int q, int& tm_,
+                                        int& tn_) {
+  if (!t.blocked) {
+    tm_ = q / t.tiles_n;
+    tn_ = q % t.tiles_n;
+    return;
+  }
+  const int g = t.gm * t.gn, B = q / g, w = q % g;
+  tm_ = (B / t.bn) * t.gm + w / t.gn;
+  tn_ = (B % t.bn) * t.gn + w % t.gn;
+}
+
 // C[m][c] = sum_k P[k*ldp + m] * Q[k*ldq + c] for m < M, c < Nc, k < Kd,
 // in kGT x kGT output tiles dealt round-robin over the team.  Each wave owns
 // a 64 x 64 quarter as 2 x 2 blocks of v_mfma_f32_32x32x2_f32; operands are
@@ -390,15 +434,30 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // float32 accumulation (v_mfma_f32_32x32x16_bf16), over the zero-padded
 // shadows: Mt, Nt multiples of kGT, Kd a multiple of kBK; every tile is
 // computed and pre / fin / put (as in team_gemm_f32) see all Mt x Nt
-// results.  Each wave owns a 64 x 64 quarter of a kGT x kGT tile; operands
-// are staged through LDS kBK k at a time with the next step prefetched into
-// registers.
+// results.  Each wave owns a 64 x 64 quarter of a kGT x kGT tile.
+//
+// Operands go from global memory straight into an LDS ring of kBfStages
+// k-steps (global_load_lds_dwordx4: no registers, no LDS store
+// instructions), kBfStages - 1 steps ahead of their use, so that many
+// steps' loads are in flight against the latency of the last-level cache
+// and HBM.  One barrier per k-step: after it, the step's slices are in LDS
+// (each wave waited for its own loads) and every wave has finished reading
+// the step whose slot the next loads overwrite.  The 16-byte chunk (row, kc)
+// of a slice (kc = k / 8 in the step) sits at chunk row * 4 + (kc ^ ((row >>
+// 1) & 3)), which keeps the operand reads (32 rows at one kc) free of bank
+// conflicts; a direct load writes 64 consecutive chunks, so each lane loads
+// the global chunk that belongs at its place.  The products run in the
+// same order as a plain k loop (per accumulator: k ascending).
+typedef __attribute__((address_space(3))) void lds_void;
 template <class Pre, class Fin, class Put>
 __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
                                const uint16_t* __restrict__ Q, int ld, int Mt,
                                int Nt, int Kd, const Team& tm, Shared& sh,
                                Pre pre, Fin fin, Put put) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  static_assert(kGT * kBK / 8 == 4 * 2 * 64, "two 64-chunk loads per wave");
+  static_assert(kBfStages >= 3, "at least two steps in flight");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
   // Arguments of an out-of-line function arrive in vector registers; the
   // sizes and the rank are the same in every lane, and saying so keeps the
@@ -409,10 +468,35 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
   const int nsteps = __builtin_amdgcn_readfirstlane(Kd) / kBK;
   const int rank = __builtin_amdgcn_readfirstlane(tm.rank);
   const int W = __builtin_amdgcn_readfirstlane(tm.W);
-  // this thread stages row tid/2, k-half (tid%2)*16 of both operand tiles
-  const int sr = tid >> 1, sk = (tid & 1) * 16;
+  // the global chunk this lane loads into each of its wave's two 64-chunk
+  // blocks of a slice
+  int goff[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int c = (wave * 2 + j) * 64 + lane, row = c >> 2;
+    goff[j] = row * ld + ((c & 3) ^ ((row >> 1) & 3)) * 8;
+  }
+  // the chunk a lane reads for rows r0 + (lane & 31) at chunk kc
+  const int rr = lane & 31, kh = lane >> 5;
+  auto chunk = [&](int row, int kc) { return row * 4 + (kc ^ ((row >> 1) & 3)); };
+  // wait for this wave's loads of the oldest step in flight (the newer
+  // kBfStages - 2 steps, 4 loads each, may still be outstanding) and for
+  // its LDS reads, then meet the other waves; a workgroup fence here would
+  // wait for every load
+  constexpr int kNW = 4 * (kBfStages - 2);
+  static_assert(kNW < 64, "vmcnt range");
+  constexpr int kWait = (kNW & 15) | ((kNW >> 4) << 14) | (7 << 4) | (0 << 8);
+  auto step_barrier = [&]() {
+    __builtin_amdgcn_s_waitcnt(kWait);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  const TileMap map = tile_map(ntiles / tiles_n, tiles_n, xcd_ranks(W));
   for (int q = rank; q < ntiles; q += W) {
-    const int m0 = (q / tiles_n) * kGT, n0 = (q % tiles_n) * kGT;
+    int ti, tj;
+    tile_of(map, q, ti, tj);
+    const int m0 = ti * kGT, n0 = tj * kGT;
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -420,61 +504,67 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-    const auto prow = gbl((const u32x4*)(P + (long long)(m0 + sr) * ld + sk));
-    const auto qrow = gbl((const u32x4*)(Q + (long long)(n0 + sr) * ld + sk));
-    // k-steps are fetched kBfPrefetch steps ahead into a ring of register
-    // sets (a fetch takes several steps' worth of MFMA time to arrive); the
-    // ring index is static because the step loop is unrolled by the ring
-    // size.  Fetches past the last step repeat it (their data is not used),
-    // so every load is unconditional.
-    u32x4 rb[kBfPrefetch][4];
-    auto fetch = [&](int s, u32x4 (&r)[4]) {
-      const int st = min(s, nsteps - 1) * (kBK / 8);  // in 16-byte units
-      r[0] = prow[st];
-      r[1] = prow[st + 1];
-      r[2] = qrow[st];
-      r[3] = qrow[st + 1];
-    };
-    // issued in ring order, as inside the loop: with the order differing
-    // between the first entry and the back edge the compiler could only
-    // wait for every outstanding load at the loop head
+    const uint16_t* const pt = P + (long long)m0 * ld;
+    const uint16_t* const qt = Q + (long long)n0 * ld;
+    // loads of step s into slot s % kBfStages; steps past the last load
+    // the last again (into slots no longer read), so that every step issues
+    // the same loads and the wait counts above hold
+    auto issue = [&](int s) {
+      const int slot = s % kBfStages;
+      const int k0 = min(s, nsteps - 1) * kBK;
 #pragma unroll
-    for (int p = 0; p < kBfPrefetch; ++p) {
-      fetch(p, rb[p]);
+      for (int j = 0; j < 2; ++j) {
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(pt + goff[j] + k0),
+            (lds_void*)&sh.t.h.ring[slot][0][(wave * 2 + j) * 64 * 8], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(qt + goff[j] + k0),
+            (lds_void*)&sh.t.h.ring[slot][1][(wave * 2 + j) * 64 * 8], 16, 0, 0);
+      }
+    };
+    // operands of one 16-k half step: a0, a1 (rows of P), b0, b1 (rows of Q)
+    auto read4 = [&](int slot, int kc, bf16x8 (&x)[4]) {
+      const uint16_t* const sp = sh.t.h.ring[slot][0];
+      const uint16_t* const sq = sh.t.h.ring[slot][1];
+      x[0] = *(const bf16x8*)&sp[chunk(wr * 64 + rr, kc) * 8];
+      x[1] = *(const bf16x8*)&sp[chunk(wr * 64 + 32 + rr, kc) * 8];
+      x[2] = *(const bf16x8*)&sq[chunk(wc * 64 + rr, kc) * 8];
+      x[3] = *(const bf16x8*)&sq[chunk(wc * 64 + 32 + rr, kc) * 8];
+    };
+#pragma unroll
+    for (int s = 0; s < kBfStages - 1; ++s) issue(s);
+    // k 0..15 of a step in x0, k 16..31 in x1; the reads of x1 run behind
+    // three products of x0, those of the next step's x0 behind the products
+    // of x1, and the barrier sits between the two halves of a step
+    bf16x8 x0[4], x1[4];
+    step_barrier();
+    issue(kBfStages - 1);
+    read4(0, kh, x0);
+    for (int s = 0; s < nsteps; ++s) {
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[0], x0[2], acc[0][0], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      read4(s % kBfStages, 2 + kh, x1);
+      __builtin_amdgcn_sched_barrier(0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[0], x0[3], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[1], x0[2], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[1], x0[3], acc[1][1], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      // also after the last step (its x0 is not used): with no branch here
+      // the products below wait for x1's reads alone
+      step_barrier();
+      issue(s + kBfStages);
+      read4((s + 1) % kBfStages, kh, x0);
+      __builtin_amdgcn_sched_barrier(0);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[0], x1[2], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[0], x1[3], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[1], x1[2], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[1], x1[3], acc[1][1], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
-    for (int s0 = 0; s0 < nsteps; s0 += kBfPrefetch) {
-#pragma unroll
-      for (int p = 0; p < kBfPrefetch; ++p) {
-        // the fetch is outside the step's condition: with a conditional
-        // fetch the count of loads issued after a buffer's own would depend
-        // on the path, and the compiler then waited for all of them
-        const bool live = s0 + p < nsteps;
-        if (live) {
-          __syncthreads();
-          *(u32x4*)&sh.t.h.lp[sr][sk] = rb[p][0];
-          *(u32x4*)&sh.t.h.lp[sr][sk + 8] = rb[p][1];
-          *(u32x4*)&sh.t.h.lq[sr][sk] = rb[p][2];
-          *(u32x4*)&sh.t.h.lq[sr][sk + 8] = rb[p][3];
-          __syncthreads();
-        }
-        fetch(s0 + p + kBfPrefetch, rb[p]);
-        if (live) {
-#pragma unroll
-          for (int ks = 0; ks < kBK; ks += 16) {
-            const int kk = ks + 8 * (lane >> 5), rr = lane & 31;
-            const bf16x8 a0 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + rr][kk];
-            const bf16x8 a1 = *(const bf16x8*)&sh.t.h.lp[wr * 64 + 32 + rr][kk];
-            const bf16x8 b0 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + rr][kk];
-            const bf16x8 b1 = *(const bf16x8*)&sh.t.h.lq[wc * 64 + 32 + rr][kk];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
-          }
-        }
-      }
-    }
+    // the repeated loads of the last step land in LDS after the loop: wait
+    // for them before the ring's slots are filled again or the LDS is
+    // given back to the caller
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 2; ++i)
