@@ -183,6 +183,9 @@ def ragged_batch(torch, F, steps):
     for p, o in zip(pairs, offs["X"]):
         m, _ = F.discretize(Xall[o:o + p.n * p.np_].reshape(p.n, p.np_))
         acc.append(scores.accuracy(m, p.perm))
+    p0 = pairs[0]
+    err0 = error_vs_oracle(Xall[:p0.n * p0.np_].reshape(p0.n, p0.np_),
+                           "config3_pair0")
     flops = sum(2.0 * p.n * p.np_ * (p.n + p.np_) * i["outer_iters"]
                 for p, i in zip(pairs, infos))
     # ALU roofline of the launch: 7 operations per entry of each pair's own
@@ -199,6 +202,7 @@ def ragged_batch(torch, F, steps):
             "accuracy_mean": float(np.mean(acc)),
             "outer_iters_mean": float(np.mean([i["outer_iters"] for i in infos])),
             "converged": int(sum(i["converged"] for i in infos)),
+            "pair0_max_abs_err_vs_fp64_oracle": err0,
             "product_tflops_in_launch": flops / (infos[0]["kernel_ms"] * 1e-3) / 1e12}
 
 

@@ -59,6 +59,8 @@ JOBS = {
     # configuration 4's evaluation size n = n' = 2000, plain FP32 settings
     "config4": lambda: write("config4", "config4_n2000_pair0",
                              synth.config4_pair(0, 2000)),
+    # the first pair of configuration 3's ragged batch (n = 57, n' = 73)
+    "config3": lambda: write("config3", "config3_pair0", synth.config3_pair(0)),
 }
 
 if __name__ == "__main__":

@@ -103,6 +103,33 @@ def test_largest_supported_size(env):
     S.close()
 
 
+def test_bf16_products_at_n4000_against_recipe_oracle(env):
+    """Configuration 4's largest size with BF16 products: one team of 256
+    workgroups (the products' output tiles handed to the XCDs in 4 x 8
+    blocks), a random start X0 so that every output tile differs, two outer
+    steps of 10 inner passes, against the oracle's bfloat16 recipe on every
+    entry (one bfloat16 ulp of the largest entry, as in the small recipe
+    tests)."""
+    torch, F = env
+    n = 4000
+    p = synth.config4_pair(11, n)
+    rng = synth.rng_for(4000, 11)
+    X0 = rng.random((n, n))
+    S = F.Solver(n, n)
+    kw = dict(max_outer=2, max_inner=10, tol_outer=1e-30)
+    X, info = solve(torch, F, S, p.A, p.B, p.K, p.lam, X0=X0,
+                    init=F.INIT_USER, precision=F.BF16, **kw)
+    A32, B32, K32, X032 = (np.asarray(a, np.float32).astype(np.float64)
+                           for a in (p.A, p.B, p.K, X0))
+    ref = O.fastpfp(A32, B32, K32, p.lam, eps1=1e-30, max_outer=2,
+                    max_inner=10, X0=X032, products="bf16")
+    print(f"n={n} BF16: max|X - ref| {np.abs(X - ref.X).max():.3e}, "
+          f"max|ref| {np.abs(ref.X).max():.3e}", flush=True)
+    assert info["status"] == 0 and info["inner_iters_total"] == 20
+    assert np.abs(X - ref.X).max() <= 2.0 ** -8 * np.abs(ref.X).max()
+    S.close()
+
+
 def test_beyond_the_largest_team_is_unsupported(env):
     torch, F = env
     S = F.Solver(4097, 4097)
