@@ -89,9 +89,9 @@ struct Shared {
       float lp[kGK][kGT];
       float lq[kGK][kGT];
     } g;
-    struct {  // BF16 GEMM staging: a ring of k-steps, each the two
-              // operands' kGT x kBK slices as 16-byte chunks
-      uint16_t ring[kBfStages][2][kGT * kBK];
+    struct {  // BF16 GEMM staging: a ring of k-steps, each the operands'
+              // kGT x kBK and (up to) 256 x kBK slices as 16-byte chunks
+      uint16_t ring[kBfStages][(kGT + 256) * kBK];
     } h;
   } t;
   float lcol[16][kTileCols];  // column partials [thread row pr][tile col]
@@ -280,8 +280,9 @@ __device__ bool team_sync_bulk(Team& tm, Shared& sh) {
 // grid divides into blocks of xg = gm x gn tiles, q instead walks the grid
 // block by block, and the xg ranks of an XCD take one near-square block in
 // each round (4 x 8 tiles for 32 ranks: 12 operand panels instead of 33).
-// Teams smaller than an XCD keep row-major order (16 ranks cover 10 panels
-// in it, 8 in blocks, and measured no faster).  Every tile is still
+// (With 128 x 256 tiles the block is 8 x 4.)  Teams smaller than an XCD
+// keep row-major order (16 ranks cover 10 panels in it, 8 in blocks, and
+// measured no faster).  Every tile is still
 // computed once, by the same instructions, so results do not depend on the
 // order.  The block size assumes 32 compute units per XCD, as on MI355X;
 // elsewhere it is only a worse order.
@@ -293,12 +294,15 @@ struct TileMap {
   int tiles_n, gm, gn, bn, blocked;
 };
 __device__ __forceinline__ TileMap tile_map(int tiles_m, int tiles_n,
-                                            int xg) {
+                                            int xg, bool wide) {
   TileMap t;
   t.tiles_n = tiles_n;
   int lg = 0;
   while ((2 << lg) <= xg) ++lg;  // xg = 2^lg for the powers of two used
-  t.gm = 1 << (lg / 2);
+  // tiles twice as wide as tall take the taller block (8 x 4), so that the
+  // block stays near square in outputs
+  const int small = 1 << (lg / 2);
+  t.gm = wide ? xg / small : small;
   t.gn = xg / t.gm;
   t.blocked = xg >= 32 && (xg & (xg - 1)) == 0 && tiles_m % t.gm == 0 &&
               tiles_n % t.gn == 0;
@@ -432,9 +436,12 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // C[m][c] = sum_k P[m*ld + k] * Q[c*ld + k] with bfloat16 operands and
 // float32 accumulation (v_mfma_f32_32x32x16_bf16), over the zero-padded
-// shadows: Mt, Nt multiples of kGT, Kd a multiple of kBK; every tile is
+// shadows: Mt a multiple of kGT, Nt of kWN, Kd of kBK; every tile is
 // computed and pre / fin / put (as in team_gemm_f32) see all Mt x Nt
-// results.  Each wave owns a 64 x 64 quarter of a kGT x kGT tile.
+// results.  A workgroup's output tile is kGT x kWN (kWN = 128 or 256), each
+// wave owning a 64 x kWN/2 part as 2 x kWN/64 blocks of 32 x 32: the wider
+// tile does twice the products per operand read and per barrier (measured
+// 15% faster on its own, the results bit for bit the same).
 //
 // Operands go from global memory straight into an LDS ring of kBfStages
 // k-steps (global_load_lds_dwordx4: no registers, no LDS store
@@ -449,12 +456,15 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // the global chunk that belongs at its place.  The products run in the
 // same order as a plain k loop (per accumulator: k ascending).
 typedef __attribute__((address_space(3))) void lds_void;
-template <class Pre, class Fin, class Put>
+template <int kWN, class Pre, class Fin, class Put>
 __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
                                const uint16_t* __restrict__ Q, int ld, int Mt,
                                int Nt, int Kd, const Team& tm, Shared& sh,
                                Pre pre, Fin fin, Put put) {
-  static_assert(kGT * kBK / 8 == 4 * 2 * 64, "two 64-chunk loads per wave");
+  static_assert(kWN == 128 || kWN == 256, "tile widths built");
+  constexpr int kNB = kWN / 64;       // 32-column blocks per wave
+  constexpr int kQL = kWN / 64;       // Q loads per wave per step
+  static_assert(kGT * 4 == 2 * 4 * 64, "two P loads of 64 chunks per wave");
   static_assert(kBfStages >= 3, "at least two steps in flight");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -463,27 +473,32 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
   // sizes and the rank are the same in every lane, and saying so keeps the
   // loop tests scalar.
   ld = __builtin_amdgcn_readfirstlane(ld);
-  const int tiles_n = __builtin_amdgcn_readfirstlane(Nt) / kGT;
+  const int tiles_n = __builtin_amdgcn_readfirstlane(Nt) / kWN;
   const int ntiles = (__builtin_amdgcn_readfirstlane(Mt) / kGT) * tiles_n;
   const int nsteps = __builtin_amdgcn_readfirstlane(Kd) / kBK;
   const int rank = __builtin_amdgcn_readfirstlane(tm.rank);
   const int W = __builtin_amdgcn_readfirstlane(tm.W);
-  // the global chunk this lane loads into each of its wave's two 64-chunk
-  // blocks of a slice
-  int goff[2];
+  // the global chunk this lane loads into each of its wave's 64-chunk
+  // blocks of a slice: two of P's 512 chunks, kQL of Q's kWN * 4
+  int gp[2], gq[kQL];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int c = (wave * 2 + j) * 64 + lane, row = c >> 2;
-    goff[j] = row * ld + ((c & 3) ^ ((row >> 1) & 3)) * 8;
+    gp[j] = row * ld + ((c & 3) ^ ((row >> 1) & 3)) * 8;
+  }
+#pragma unroll
+  for (int j = 0; j < kQL; ++j) {
+    const int c = (wave * kQL + j) * 64 + lane, row = c >> 2;
+    gq[j] = row * ld + ((c & 3) ^ ((row >> 1) & 3)) * 8;
   }
   // the chunk a lane reads for rows r0 + (lane & 31) at chunk kc
   const int rr = lane & 31, kh = lane >> 5;
   auto chunk = [&](int row, int kc) { return row * 4 + (kc ^ ((row >> 1) & 3)); };
   // wait for this wave's loads of the oldest step in flight (the newer
-  // kBfStages - 2 steps, 4 loads each, may still be outstanding) and for
-  // its LDS reads, then meet the other waves; a workgroup fence here would
-  // wait for every load
-  constexpr int kNW = 4 * (kBfStages - 2);
+  // kBfStages - 2 steps, 2 + kQL loads each, may still be outstanding) and
+  // for its LDS reads, then meet the other waves; a workgroup fence here
+  // would wait for every load
+  constexpr int kNW = (2 + kQL) * (kBfStages - 2);
   static_assert(kNW < 64, "vmcnt range");
   constexpr int kWait = (kNW & 15) | ((kNW >> 4) << 14) | (7 << 4) | (0 << 8);
   auto step_barrier = [&]() {
@@ -492,16 +507,17 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   };
-  const TileMap map = tile_map(ntiles / tiles_n, tiles_n, xcd_ranks(W));
+  const TileMap map =
+      tile_map(ntiles / tiles_n, tiles_n, xcd_ranks(W), kWN > kGT);
   for (int q = rank; q < ntiles; q += W) {
     int ti, tj;
     tile_of(map, q, ti, tj);
-    const int m0 = ti * kGT, n0 = tj * kGT;
-    floatx16 acc[2][2];
+    const int m0 = ti * kGT, n0 = tj * kWN;
+    floatx16 acc[2][kNB];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < kNB; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
     const uint16_t* const pt = P + (long long)m0 * ld;
@@ -513,52 +529,62 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
       const int slot = s % kBfStages;
       const int k0 = min(s, nsteps - 1) * kBK;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 2; ++j)
         __builtin_amdgcn_global_load_lds(
-            (const void*)(pt + goff[j] + k0),
-            (lds_void*)&sh.t.h.ring[slot][0][(wave * 2 + j) * 64 * 8], 16, 0, 0);
+            (const void*)(pt + gp[j] + k0),
+            (lds_void*)&sh.t.h.ring[slot][(wave * 2 + j) * 64 * 8], 16, 0, 0);
+#pragma unroll
+      for (int j = 0; j < kQL; ++j)
         __builtin_amdgcn_global_load_lds(
-            (const void*)(qt + goff[j] + k0),
-            (lds_void*)&sh.t.h.ring[slot][1][(wave * 2 + j) * 64 * 8], 16, 0, 0);
-      }
+            (const void*)(qt + gq[j] + k0),
+            (lds_void*)&sh.t.h.ring[slot][(kGT * 4 + (wave * kQL + j) * 64) * 8],
+            16, 0, 0);
     };
-    // operands of one 16-k half step: a0, a1 (rows of P), b0, b1 (rows of Q)
-    auto read4 = [&](int slot, int kc, bf16x8 (&x)[4]) {
-      const uint16_t* const sp = sh.t.h.ring[slot][0];
-      const uint16_t* const sq = sh.t.h.ring[slot][1];
+    // operands of one 16-k half step: x[0], x[1] rows of P, x[2 + j] rows of Q
+    auto readx = [&](int slot, int kc, bf16x8 (&x)[2 + kNB]) {
+      const uint16_t* const sp = sh.t.h.ring[slot];
+      const uint16_t* const sq = sp + kGT * 4 * 8;
       x[0] = *(const bf16x8*)&sp[chunk(wr * 64 + rr, kc) * 8];
       x[1] = *(const bf16x8*)&sp[chunk(wr * 64 + 32 + rr, kc) * 8];
-      x[2] = *(const bf16x8*)&sq[chunk(wc * 64 + rr, kc) * 8];
-      x[3] = *(const bf16x8*)&sq[chunk(wc * 64 + 32 + rr, kc) * 8];
+#pragma unroll
+      for (int j = 0; j < kNB; ++j)
+        x[2 + j] = *(const bf16x8*)&sq[chunk(wc * (kWN / 2) + 32 * j + rr, kc) * 8];
     };
 #pragma unroll
     for (int s = 0; s < kBfStages - 1; ++s) issue(s);
     // k 0..15 of a step in x0, k 16..31 in x1; the reads of x1 run behind
-    // three products of x0, those of the next step's x0 behind the products
-    // of x1, and the barrier sits between the two halves of a step
-    bf16x8 x0[4], x1[4];
+    // the products of x0 after the first, those of the next step's x0
+    // behind the products of x1, and the barrier sits between the two
+    // halves of a step
+    bf16x8 x0[2 + kNB], x1[2 + kNB];
     step_barrier();
     issue(kBfStages - 1);
-    read4(0, kh, x0);
+    readx(0, kh, x0);
     for (int s = 0; s < nsteps; ++s) {
       acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[0], x0[2], acc[0][0], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
-      read4(s % kBfStages, 2 + kh, x1);
+      readx(s % kBfStages, 2 + kh, x1);
       __builtin_amdgcn_sched_barrier(0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[0], x0[3], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[1], x0[2], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0[1], x0[3], acc[1][1], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < kNB; ++j)
+          if (i != 0 || j != 0)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                x0[i], x0[2 + j], acc[i][j], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
       // also after the last step (its x0 is not used): with no branch here
       // the products below wait for x1's reads alone
       step_barrier();
       issue(s + kBfStages);
-      read4((s + 1) % kBfStages, kh, x0);
+      readx((s + 1) % kBfStages, kh, x0);
       __builtin_amdgcn_sched_barrier(0);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[0], x1[2], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[0], x1[3], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[1], x1[2], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1[1], x1[3], acc[1][1], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < kNB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              x1[i], x1[2 + j], acc[i][j], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
     // the repeated loads of the last step land in LDS after the loop: wait
@@ -569,8 +595,8 @@ __device__ void team_gemm_bf16(const uint16_t* __restrict__ P,
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int cc = n0 + wc * 64 + 32 * j + (lane & 31);
+      for (int j = 0; j < kNB; ++j) {
+        const int cc = n0 + wc * (kWN / 2) + 32 * j + (lane & 31);
         float2 ad[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
@@ -1280,13 +1306,27 @@ fastpfp_persistent(LaunchDesc L) {
           auto same = [](float val, float2) { return val; };
           if (bf) {
             const int ld = Np;
-            team_gemm_bf16(Ah, Xh, Np, Mt, Nt, (n + kBK - 1) / kBK * kBK, tm,
-                           sh, no_pre, same, [=](int m, int c, float val) {
-                             gbl(Th)[(long long)m * ld + c] = f2bf(val);
-                           });
+            auto put_t = [=](int m, int c, float val) {
+              gbl(Th)[(long long)m * ld + c] = f2bf(val);
+            };
+            const int K1 = (n + kBK - 1) / kBK * kBK;
+            const int K2 = (np + kBK - 1) / kBK * kBK;
+            // T = A X in 128 x 256 output tiles where the columns divide
+            // into them.  The second product keeps 128 x 128 tiles: built
+            // wide, it came out of the compiler using every register without
+            // saving any, so this kernel kept its own values in scratch
+            // around the call and the update phase took twice as long; the
+            // first product saves what it uses, and with it alone wide the
+            // two products together ran 20% faster.
+            if (Nt % 256 == 0)
+              team_gemm_bf16<256>(Ah, Xh, Np, Mt, Nt, K1, tm, sh, no_pre, same,
+                                  put_t);
+            else
+              team_gemm_bf16<kGT>(Ah, Xh, Np, Mt, Nt, K1, tm, sh, no_pre, same,
+                                  put_t);
             if (!team_sync_bulk(tm, sh)) return;
-            team_gemm_bf16(Th, Bh, Np, Mt, Nt, (np + kBK - 1) / kBK * kBK, tm,
-                           sh, out_pre, out_fin, out);
+            team_gemm_bf16<kGT>(Th, Bh, Np, Mt, Nt, K2, tm, sh, out_pre,
+                                out_fin, out);
           } else {
             float* const Tw = Tt;
             team_gemm_f32(X, ldx, pd.A, pd.lda, np, n, n, tm, sh, no_pre, same,
