@@ -105,8 +105,9 @@ def test_largest_supported_size(env):
 
 def test_bf16_products_at_n4000_against_recipe_oracle(env):
     """Configuration 4's largest size with BF16 products: one team of 256
-    workgroups (the products' output tiles handed to the XCDs in 4 x 8
-    blocks), a random start X0 so that every output tile differs, two outer
+    workgroups (T = A X in 128 x 256 output tiles handed to the XCDs in
+    8 x 4 blocks, the second product in 128 x 128 tiles in 4 x 8 blocks), a
+    random start X0 so that every output tile differs, two outer
     steps of 10 inner passes, against the oracle's bfloat16 recipe on every
     entry (one bfloat16 ulp of the largest entry, as in the small recipe
     tests)."""
