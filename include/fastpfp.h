@@ -343,10 +343,14 @@ fastpfp_status fastpfp_warmstart(fastpfp_t h, int n, int np, const float* A,
                                  int ldg, int fdim, int flags, float* X0,
                                  int ldx);
 
-/* fastpfp_warmstart for a packed batch, enqueued back to back with one
- * synchronisation at the end.  Pair b: A + offA_host[b] (n x n, pitch n),
- * B + offB_host[b] (n' x n', pitch n'), F + offF_host[b] (n x fdim, pitch
- * fdim), G + offG_host[b] (n' x fdim), X + offX_host[b] (n x n', pitch n').
+/* fastpfp_warmstart for a packed batch, with one synchronisation at the
+ * end: the pairs' forward passes run on four streams of the handle at once
+ * (pair b on stream b % 4, after the work already on the handle's stream;
+ * that stream waits for all four before the call returns, and the results
+ * are the same as one pair at a time).  Pair b: A + offA_host[b] (n x n,
+ * pitch n), B + offB_host[b] (n' x n', pitch n'), F + offF_host[b]
+ * (n x fdim, pitch fdim), G + offG_host[b] (n' x fdim), X + offX_host[b]
+ * (n x n', pitch n').
  * F, G and their offsets may be NULL iff fdim == 0.  status_host (nullable,
  * batch entries) receives OK or NUMERIC per pair; every pair is computed and
  * the call returns the first failing status. */

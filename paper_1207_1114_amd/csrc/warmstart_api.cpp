@@ -44,6 +44,16 @@ struct WarmState {
   int* bad = nullptr;
   int* bads = nullptr;  // one flag per pair of a batched call
   int bads_cap = 0;
+  // a batched call runs its pairs' forward passes on kLanes streams at once
+  // (each pass is a dozen small launches): a stream, an event and the node
+  // buffers of both sides per lane
+  static constexpr int kLanes = 4;
+  hipStream_t lane_s[kLanes] = {};
+  hipEvent_t lane_ev[kLanes] = {};
+  hipEvent_t start_ev = nullptr;
+  void* lbuf = nullptr;
+  int lane_cap = 0;
+  Side lside[kLanes][2];
 
   float* params() { return pbuf; }
   float* grad() { return pbuf + fpws::kNumParams; }
@@ -57,6 +67,12 @@ void warm_free(WarmState* w) {
   if (w->nbuf) (void)hipFree(w->nbuf);
   if (w->qbuf) (void)hipFree(w->qbuf);
   if (w->bads) (void)hipFree(w->bads);
+  if (w->lbuf) (void)hipFree(w->lbuf);
+  for (int l = 0; l < WarmState::kLanes; ++l) {
+    if (w->lane_s[l]) (void)hipStreamDestroy(w->lane_s[l]);
+    if (w->lane_ev[l]) (void)hipEventDestroy(w->lane_ev[l]);
+  }
+  if (w->start_ev) (void)hipEventDestroy(w->start_ev);
   delete w;
 }
 
@@ -76,18 +92,41 @@ WarmState* state(fastpfp_t h) {
   return h->warm;
 }
 
+// Bytes of one side's node buffers for `c` rows.
+size_t side_bytes(size_t c) {
+  return up256(c * sizeof(float)) + up256(c * sizeof(double)) + 256 +
+         up256(c * sizeof(float) * fpws::kDin) +
+         2 * up256(c * sizeof(float) * fpws::kH) +
+         up256(c * sizeof(float) * fpws::kDout) +
+         up256(c * sizeof(float) * fpws::kDout) +
+         2 * up256(c * sizeof(float) * fpws::kH);
+}
+
+// Carves one side's buffers for `c` rows out of p.
+char* carve_side(char* p, size_t c, Side& d) {
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += up256(bytes);
+    return r;
+  };
+  d.deg = (float*)take(c * sizeof(float));
+  d.wdeg = (double*)take(c * sizeof(double));
+  d.means = (double*)take(2 * sizeof(double));
+  d.x = (float*)take(c * sizeof(float) * fpws::kDin);
+  d.h1 = (float*)take(c * sizeof(float) * fpws::kH);
+  d.h2 = (float*)take(c * sizeof(float) * fpws::kH);
+  d.e = (float*)take(c * sizeof(float) * fpws::kDout);
+  d.dE = (float*)take(c * sizeof(float) * fpws::kDout);
+  d.d2 = (float*)take(c * sizeof(float) * fpws::kH);
+  d.d1 = (float*)take(c * sizeof(float) * fpws::kH);
+  return p;
+}
+
 // Node buffers for both sides, grown to hold `nodes` rows each.
 fastpfp_status ensure_nodes(fastpfp_t h, int nodes) {
   WarmState* w = state(h);
   if (nodes <= w->node_cap) return FASTPFP_OK;
-  const size_t c = (size_t)nodes;
-  const size_t per_side =
-      up256(c * sizeof(float)) + up256(c * sizeof(double)) + 256 +
-      up256(c * sizeof(float) * fpws::kDin) +
-      2 * up256(c * sizeof(float) * fpws::kH) +
-      up256(c * sizeof(float) * fpws::kDout) +
-      up256(c * sizeof(float) * fpws::kDout) +
-      2 * up256(c * sizeof(float) * fpws::kH);
+  const size_t c = (size_t)nodes, per_side = side_bytes(c);
   if (w->nbuf) (void)hipFree(w->nbuf);
   w->nbuf = nullptr;
   w->node_cap = 0;
@@ -97,25 +136,49 @@ fastpfp_status ensure_nodes(fastpfp_t h, int nodes) {
                 2 * per_side);
   }
   char* p = (char*)w->nbuf;
-  auto take = [&](size_t bytes) {
-    char* r = p;
-    p += up256(bytes);
-    return r;
-  };
-  for (int s = 0; s < 2; ++s) {
-    Side& d = w->side[s];
-    d.deg = (float*)take(c * sizeof(float));
-    d.wdeg = (double*)take(c * sizeof(double));
-    d.means = (double*)take(2 * sizeof(double));
-    d.x = (float*)take(c * sizeof(float) * fpws::kDin);
-    d.h1 = (float*)take(c * sizeof(float) * fpws::kH);
-    d.h2 = (float*)take(c * sizeof(float) * fpws::kH);
-    d.e = (float*)take(c * sizeof(float) * fpws::kDout);
-    d.dE = (float*)take(c * sizeof(float) * fpws::kDout);
-    d.d2 = (float*)take(c * sizeof(float) * fpws::kH);
-    d.d1 = (float*)take(c * sizeof(float) * fpws::kH);
-  }
+  for (int s = 0; s < 2; ++s) p = carve_side(p, c, w->side[s]);
   w->node_cap = nodes;
+  return FASTPFP_OK;
+}
+
+// The lanes of a batched forward pass: streams and events (created once, at
+// the default priority) and node buffers for `nodes` rows per side.
+fastpfp_status ensure_lanes(fastpfp_t h, int nodes) {
+  WarmState* w = state(h);
+  if (!w->start_ev &&
+      hipEventCreateWithFlags(&w->start_ev, hipEventDisableTiming) !=
+          hipSuccess) {
+    w->start_ev = nullptr;
+    return fail(h, FASTPFP_ERR_HIP, "cannot create an event");
+  }
+  for (int l = 0; l < WarmState::kLanes; ++l) {
+    if (!w->lane_s[l] &&
+        hipStreamCreateWithFlags(&w->lane_s[l], hipStreamNonBlocking) !=
+            hipSuccess) {
+      w->lane_s[l] = nullptr;
+      return fail(h, FASTPFP_ERR_HIP, "cannot create a stream");
+    }
+    if (!w->lane_ev[l] &&
+        hipEventCreateWithFlags(&w->lane_ev[l], hipEventDisableTiming) !=
+            hipSuccess) {
+      w->lane_ev[l] = nullptr;
+      return fail(h, FASTPFP_ERR_HIP, "cannot create an event");
+    }
+  }
+  if (nodes <= w->lane_cap) return FASTPFP_OK;
+  const size_t c = (size_t)nodes, per_side = side_bytes(c);
+  const size_t bytes = 2 * WarmState::kLanes * per_side;
+  if (w->lbuf) (void)hipFree(w->lbuf);
+  w->lbuf = nullptr;
+  w->lane_cap = 0;
+  if (hipMalloc(&w->lbuf, bytes) != hipSuccess) {
+    w->lbuf = nullptr;
+    return fail(h, FASTPFP_ERR_NOMEM, "cannot allocate %zu bytes", bytes);
+  }
+  char* p = (char*)w->lbuf;
+  for (int l = 0; l < WarmState::kLanes; ++l)
+    for (int s = 0; s < 2; ++s) p = carve_side(p, c, w->lside[l][s]);
+  w->lane_cap = nodes;
   return FASTPFP_OK;
 }
 
@@ -182,8 +245,8 @@ GemmArgs gemm(const float* A, long long sam, long long sak, const float* B,
 
 // Degrees, their means and the 48 features of one graph into d.x.
 fastpfp_status features(fastpfp_t h, const Side& d, int n, const float* A,
-                        int lda, const float* F, int ldf, int fdim) {
-  hipStream_t s = h->stream;
+                        int lda, const float* F, int ldf, int fdim,
+                        hipStream_t s) {
   WSCHK(fpws_degree(A, lda, n, d.deg, d.wdeg, s));
   WSCHK(fpws_means(d.deg, d.wdeg, n, d.means, s));
   WSCHK(fpws_features(A, lda, n, d.deg, d.wdeg, d.means, F, ldf,
@@ -193,9 +256,8 @@ fastpfp_status features(fastpfp_t h, const Side& d, int n, const float* A,
 
 // h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2), e = h2 W3^T + b3.
 fastpfp_status mlp_forward(fastpfp_t h, const Side& d, int n,
-                           const float* P, bool bf16) {
+                           const float* P, bool bf16, hipStream_t s) {
   using namespace fpws;
-  hipStream_t s = h->stream;
   GemmArgs g = gemm(d.x, kDin, 1, P + kOffW1, 1, kDin, d.h1, kH, n, kH, kDin);
   g.bias = P + kOffB1;
   g.relu = 1;
@@ -293,15 +355,18 @@ fastpfp_status finish(fastpfp_t h, const char* what) {
 fastpfp_status enqueue_x0(fastpfp_t h, int n, int np, const float* A, int lda,
                           const float* B, int ldb, const float* F, int ldf,
                           const float* G, int ldg, int fdim, bool bf16,
-                          float* X0, int ldx, int* bad_dev) {
+                          float* X0, int ldx, int* bad_dev, const Side& a,
+                          const Side& b, hipStream_t s) {
   WarmState* w = h->warm;
-  hipStream_t s = h->stream;
   fastpfp_status st;
-  const Side &a = w->side[0], &b = w->side[1];
-  if ((st = features(h, a, n, A, lda, F, ldf, fdim)) != FASTPFP_OK) return st;
-  if ((st = features(h, b, np, B, ldb, G, ldg, fdim)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, a, n, w->params(), bf16)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, b, np, w->params(), bf16)) != FASTPFP_OK) return st;
+  if ((st = features(h, a, n, A, lda, F, ldf, fdim, s)) != FASTPFP_OK)
+    return st;
+  if ((st = features(h, b, np, B, ldb, G, ldg, fdim, s)) != FASTPFP_OK)
+    return st;
+  if ((st = mlp_forward(h, a, n, w->params(), bf16, s)) != FASTPFP_OK)
+    return st;
+  if ((st = mlp_forward(h, b, np, w->params(), bf16, s)) != FASTPFP_OK)
+    return st;
   GemmArgs g = gemm(a.e, fpws::kDout, 1, b.e, 1, fpws::kDout, X0, ldx, n, np,
                     fpws::kDout);
   g.logtau = w->params() + fpws::kOffTau;
@@ -408,7 +473,8 @@ fastpfp_status fastpfp_warmstart(fastpfp_t h, int n, int np, const float* A,
   HIPCHK(h, fpws_fill_int(w->bad, 1, 0, h->stream));
   if ((st = enqueue_x0(h, n, np, A, lda, B, ldb, F, ldf, G, ldg, fdim,
                        (flags & FASTPFP_WS_BF16_WEIGHTS) != 0, X0, ldx,
-                       w->bad)) != FASTPFP_OK)
+                       w->bad, w->side[0], w->side[1], h->stream)) !=
+      FASTPFP_OK)
     return st;
   return finish(h, "the warm start");
 }
@@ -439,7 +505,7 @@ fastpfp_status fastpfp_warmstart_batched(
       return fail(h, FASTPFP_ERR_INVALID_ARG, "pair %d: negative offset", b);
     nodes = std::max(nodes, std::max(n, np));
   }
-  if ((st = ensure_nodes(h, nodes)) != FASTPFP_OK) return st;
+  if ((st = ensure_lanes(h, nodes)) != FASTPFP_OK) return st;
   if ((st = ensure_pair(h, 0, 0)) != FASTPFP_OK) return st;
   WarmState* w = h->warm;
   if (batch > w->bads_cap) {
@@ -455,15 +521,31 @@ fastpfp_status fastpfp_warmstart_batched(
   hipStream_t s = h->stream;
   HIPCHK(h, fpws_fill_int(w->bads, batch, 0, s));
   const bool bf16 = (flags & FASTPFP_WS_BF16_WEIGHTS) != 0;
+  // pair b on lane b % kLanes: the lanes start after the caller's stream has
+  // cleared the flags (and whatever it ran before), and the caller's stream
+  // waits for all of them; each lane has its own node buffers, and every
+  // pair writes only its own X0 and flag
+  constexpr int L = WarmState::kLanes;
+  HIPCHK(h, hipEventRecord(w->start_ev, s));
+  for (int l = 0; l < L; ++l)
+    HIPCHK(h, hipStreamWaitEvent(w->lane_s[l], w->start_ev, 0));
   for (int b = 0; b < batch; ++b) {
-    const int n = n_host[b], np = np_host[b];
+    const int n = n_host[b], np = np_host[b], l = b % L;
     const float* Fb = fdim > 0 ? F + offF_host[b] : nullptr;
     const float* Gb = fdim > 0 ? G + offG_host[b] : nullptr;
-    if ((st = enqueue_x0(h, n, np, A + offA_host[b], n, B + offB_host[b], np,
-                         Fb, fdim, Gb, fdim, fdim, bf16, X + offX_host[b], np,
-                         w->bads + b)) != FASTPFP_OK)
-      return st;
+    st = enqueue_x0(h, n, np, A + offA_host[b], n, B + offB_host[b], np, Fb,
+                    fdim, Gb, fdim, fdim, bf16, X + offX_host[b], np,
+                    w->bads + b, w->lside[l][0], w->lside[l][1],
+                    w->lane_s[l]);
+    if (st != FASTPFP_OK) break;
   }
+  // joined even after a failed enqueue, so that no lane is left running
+  // work the caller's stream does not wait for
+  for (int l = 0; l < L; ++l) {
+    HIPCHK(h, hipEventRecord(w->lane_ev[l], w->lane_s[l]));
+    HIPCHK(h, hipStreamWaitEvent(s, w->lane_ev[l], 0));
+  }
+  if (st != FASTPFP_OK) return st;
   std::vector<int> bad(batch);
   HIPCHK(h, hipMemcpyAsync(bad.data(), w->bads, sizeof(int) * batch,
                            hipMemcpyDeviceToHost, s));
@@ -503,10 +585,12 @@ fastpfp_status fastpfp_warmstart_grad(fastpfp_t h, int n, int np,
   float* Gr = w->grad();
   HIPCHK(h, fpws_fill_int(w->bad, 1, 0, s));
   const Side &a = w->side[0], &b = w->side[1];
-  if ((st = features(h, a, n, A, lda, F, ldf, fdim)) != FASTPFP_OK) return st;
-  if ((st = features(h, b, np, B, ldb, G, ldg, fdim)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, a, n, P, false)) != FASTPFP_OK) return st;
-  if ((st = mlp_forward(h, b, np, P, false)) != FASTPFP_OK) return st;
+  if ((st = features(h, a, n, A, lda, F, ldf, fdim, s)) != FASTPFP_OK)
+    return st;
+  if ((st = features(h, b, np, B, ldb, G, ldg, fdim, s)) != FASTPFP_OK)
+    return st;
+  if ((st = mlp_forward(h, a, n, P, false, s)) != FASTPFP_OK) return st;
+  if ((st = mlp_forward(h, b, np, P, false, s)) != FASTPFP_OK) return st;
   using fpws::kDout;
   GemmArgs g = gemm(a.e, kDout, 1, b.e, 1, kDout, w->S, np, n, np, kDout);
   g.logtau = P + fpws::kOffTau;
