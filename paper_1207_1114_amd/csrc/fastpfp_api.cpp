@@ -626,6 +626,10 @@ fastpfp_status fastpfp_create(fastpfp_t* out, int device, int max_n,
     delete h;
     return FASTPFP_ERR_HIP;
   }
+  // the warm start's streams are made with the handle: made later, after
+  // the process's first solver launch, they were measured to run one after
+  // another instead of side by side
+  fpfp::warm_prepare(h);
   *out = h;
   return FASTPFP_OK;
 }

@@ -10,9 +10,11 @@
 
 #include "fastpfp.h"
 
+struct fastpfp_ctx;
 namespace fpfp {
 struct WarmState;                  // learned warm start (warmstart_api.cpp)
 void warm_free(WarmState* w);      // releases its device memory
+void warm_prepare(fastpfp_ctx* h); // creates its streams (best effort)
 }  // namespace fpfp
 
 struct fastpfp_ctx {

@@ -76,6 +76,26 @@ void warm_free(WarmState* w) {
   delete w;
 }
 
+void warm_prepare(fastpfp_ctx* h) {
+  if (!h->warm) h->warm = new WarmState;
+  WarmState* w = h->warm;
+  // failures are left for ensure_lanes to report when the lanes are used
+  if (!w->start_ev &&
+      hipEventCreateWithFlags(&w->start_ev, hipEventDisableTiming) !=
+          hipSuccess)
+    w->start_ev = nullptr;
+  for (int l = 0; l < WarmState::kLanes; ++l) {
+    if (!w->lane_s[l] &&
+        hipStreamCreateWithFlags(&w->lane_s[l], hipStreamNonBlocking) !=
+            hipSuccess)
+      w->lane_s[l] = nullptr;
+    if (!w->lane_ev[l] &&
+        hipEventCreateWithFlags(&w->lane_ev[l], hipEventDisableTiming) !=
+            hipSuccess)
+      w->lane_ev[l] = nullptr;
+  }
+}
+
 }  // namespace fpfp
 
 namespace {
