@@ -297,6 +297,31 @@ def test_bf16_products_match_recipe_oracle(env, n, m):
     assert info["outer_iters"] == ref.outer_iters
 
 
+@pytest.mark.parametrize("n,m", [(250, 256), (256, 250), (300, 500),
+                                 (500, 300), (400, 400)])
+def test_bf16_products_one_step_match_recipe_oracle(env, n, m):
+    """The BF16 products at sizes whose n' pads to a multiple of 256 (256,
+    512: T = A X in 128 x 256 tiles) and to 384 and 512 the other way round,
+    one outer step against the oracle's bfloat16 recipe, to one bfloat16
+    ulp of the largest entry.  (Over five steps the rounding differences
+    between float32 and float64 accumulation grow to 2-3 ulps at these sizes
+    through the iteration itself; the kernel before the wide tiles gives the
+    same iterates bit for bit.)"""
+    torch, F, S = env
+    rng = synth.rng_for(98, n * 1000 + m)
+    A = synth.random_weighted_graph(rng, n, 0.3)
+    B = synth.random_weighted_graph(rng, m, 0.3)
+    K = rng.random((n, m))
+    p = synth.GraphPair(A, B, K, 0.5, np.full(n, -1))
+    kw = dict(max_outer=1, max_inner=120)
+    X, info, _ = gpu_solve(env, p, lambda_=0.5, precision=F.BF16, **kw)
+    ref = O.fastpfp(A, B, K, 0.5, products="bf16", **kw)
+    print(f"n={n} n'={m}: max|X - ref| {np.abs(X - ref.X).max():.2e}",
+          flush=True)
+    assert np.abs(X - ref.X).max() <= 2.0 ** -8 * np.abs(ref.X).max()
+    assert info["outer_iters"] == ref.outer_iters == 1
+
+
 def test_bf16_and_fp32_config2_full_size(env):
     """Config 2 (n = 1000, n' = 1200, 200 outliers): every entry of the FP32
     form within 1e-4 max X of the stored FP64 oracle with the same matching;

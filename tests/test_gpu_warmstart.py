@@ -223,6 +223,36 @@ def test_a_few_adam_steps_lower_the_loss(env):
     assert losses[-1] < 0.5 * losses[0], losses[::6]
 
 
+def test_batched_x0_on_every_stream_equals_single(env):
+    """Twelve pairs of mixed sizes: the batched call spreads them over its
+    four streams (three pairs each, of different sizes, sharing that
+    stream's node buffers in turn); every X0 equals the one-pair call bit
+    for bit."""
+    torch, F, S = env
+    shapes = [(40, 60), (300, 280), (17, 17), (128, 200), (250, 250),
+              (90, 33), (64, 64), (199, 301), (5, 9), (260, 140), (120, 120),
+              (77, 150)]
+    pairs = [pair(0, n, m, 30 + k) for k, (n, m) in enumerate(shapes)]
+    S.warmstart_load(params(4))
+    cat = lambda xs: dev(torch, np.concatenate([np.ravel(x) for x in xs]))
+    offs = lambda xs: np.cumsum([0] + [np.size(x) for x in xs[:-1]])
+    As, Bs = [p[0] for p in pairs], [p[1] for p in pairs]
+    Fs, Gs = [p[2] for p in pairs], [p[3] for p in pairs]
+    Xs = [np.zeros(s) for s in shapes]
+    X = cat(Xs)
+    st = S.warmstart_batched([s[0] for s in shapes], [s[1] for s in shapes],
+                             cat(As), offs(As), cat(Bs), offs(Bs), cat(Fs),
+                             offs(Fs), cat(Gs), offs(Gs), 16, X, offs(Xs),
+                             bf16_weights=True)
+    assert st == [0] * len(shapes)
+    Xh = X.cpu().numpy()
+    for k, ((n, m), o) in enumerate(zip(shapes, offs(Xs))):
+        Xk = torch.zeros(n, m, device="cuda:0")
+        S.warmstart(*(dev(torch, a) for a in pairs[k]), Xk, bf16_weights=True)
+        np.testing.assert_array_equal(Xh[o:o + n * m].reshape(n, m),
+                                      Xk.cpu().numpy())
+
+
 def test_batched_x0_equals_single_and_isolates_a_bad_pair(env):
     torch, F, S = env
     shapes = [(70, 90), (130, 100), (1, 1), (64, 64), (200, 257)]
